@@ -1,0 +1,171 @@
+/*
+ * libkrp -- Khatri-Rao random projections (KRP) on AMD Instinct MI355X (gfx950).
+ *
+ * C ABI of the sketching and compression calls of Saibaba, Verma and Ballard,
+ * "Improved Analysis of Khatri-Rao Random Projections and Applications":
+ *   krp_sketch          KRP sketch of mode unfoldings of a dense tensor
+ *                       (the MTTKRP of Algorithm 7, step 3).
+ *   krp_hosvd           randomized HOSVD with KRPs (Algorithm 7).
+ *   krp_sthosvd         randomized STHOSVD with KRPs (Algorithm 8).
+ *   krp_hankel_lowrank  single-pass randomized SVD of block-Hankel matrices
+ *                       with KRPs (Algorithm 6 with the Hankel structure of
+ *                       Section 4.2), batched over instances of uneven size.
+ *
+ * Conventions
+ *   - Pointers named "device" point to GPU memory of the current HIP device;
+ *     all others are host memory.  The caller owns every buffer it passes; the
+ *     library never frees caller memory.
+ *   - Tensors are dense and in Kolda order: x_{i_1..i_d} sits at offset
+ *     i_1 + n_1 (i_2 + n_2 (i_3 + ...)), i.e. mode 1 varies fastest (dims[0]
+ *     in the arrays below).  Matrices are column-major.
+ *   - Every call is stream-ordered and asynchronous on `stream` (a
+ *     hipStream_t, NULL for the default stream) unless it needs to return a
+ *     numerical status (see krp_opts.status_dev).
+ *   - Argument errors are detected before any HIP call and return KRP_EINVAL
+ *     (krp_last_error() gives the reason); no exception crosses the ABI.
+ *   - Random factors: every entry of every Gaussian factor is a function of
+ *     (seed, draw, sketched mode, factor id, row, column, instance) through
+ *     Philox4x64-10 and a fixed Box-Muller transform, so results are
+ *     reproducible across calls and independent of tiling.
+ *   - Calls that use the library-owned workspace may run concurrently on
+ *     different streams (each stream gets its own workspace).
+ */
+#ifndef KRP_H
+#define KRP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Return codes. */
+enum {
+  KRP_OK = 0,
+  KRP_EINVAL = 1,      /* invalid argument (reported before any GPU work) */
+  KRP_ENOMEM = 2,      /* device allocation failed or workspace too small */
+  KRP_EHIP = 3,        /* a HIP runtime call failed */
+  KRP_ECHOL = 4,       /* CholeskyQR broke down even after the shifted fallback */
+  KRP_ENONFINITE = 5,  /* a non-finite value reached an orthonormalisation */
+  KRP_ENODEV = 6       /* no usable gfx950 device */
+};
+
+/* Storage type of tensors, Hankel data and outputs. */
+enum { KRP_F64 = 0, KRP_F32 = 1 };
+
+/* Arithmetic of the bulk contractions (sketch and TTM).  Gram matrices,
+ * Cholesky factors, R^{-1}, the least-squares solve and the small SVDs are
+ * always fp64.  KRP_P_BF16X3 multiplies split bf16 pairs (hi*hi + hi*lo +
+ * lo*hi) on the matrix cores with fp32 accumulation. */
+enum { KRP_P_FP64 = 0, KRP_P_FP32 = 1, KRP_P_BF16 = 2, KRP_P_BF16X3 = 3 };
+
+/* Bits of the device status word (krp_opts.status_dev). */
+enum {
+  KRP_STAT_CHOL_SHIFT = 1,  /* shifted CholeskyQR fallback taken (result still valid) */
+  KRP_STAT_CHOL_FAIL = 2,   /* breakdown after the fallback (maps to KRP_ECHOL) */
+  KRP_STAT_NONFINITE = 4    /* non-finite input to a QR (maps to KRP_ENONFINITE) */
+};
+
+/* krp_opts.flags */
+enum {
+  KRP_FLAG_NO_GRAPH = 1,   /* launch kernels directly instead of a cached HIP graph */
+  KRP_FLAG_AUTOTUNE = 2    /* time candidate tilings on first use of a shape */
+};
+
+typedef struct krp_opts {
+  uint64_t seed;          /* Philox key word 0 */
+  uint32_t draw;          /* call-level stream id (counter word 2, bits 32..63) */
+  int32_t prec;           /* KRP_P_*; KRP_P_FP64 is required for KRP_F64 data */
+  int32_t truncate;       /* 0: rank-ell Tucker/Hankel output as in Algorithms 7/8;
+                             1: fp64 truncation of the ell-sized core to the
+                             target ranks (ST-HOSVD of the core) */
+  int32_t flags;          /* KRP_FLAG_* */
+  const int32_t* order;   /* host, d entries: STHOSVD mode order (NULL: 0..d-1) */
+  void* workspace;        /* device; NULL: library-owned, cached per stream */
+  size_t workspace_bytes; /* size of `workspace` (see krp_*_workspace_size) */
+  int32_t* status_dev;    /* device int: when non-NULL the call does not
+                             synchronise; the status bits are OR-ed into it */
+  double* rel_err;        /* host, optional out: ||X - Xhat||_F / ||X||_F
+                             (Tucker calls; forces a synchronisation) */
+} krp_opts;
+
+/* Fills *o with defaults: seed 2507, draw 0, KRP_P_FP32, no truncation, no
+ * flags, natural order, library workspace, synchronous status. */
+void krp_opts_default(krp_opts* o);
+
+/* KRP sketches of one or more mode unfoldings (Algorithm 7, step 3):
+ *   Y_j = X_(m) (Omega_d kr ... kr Omega_{m+1} kr Omega_{m-1} kr ... kr Omega_1),
+ * m = modes[j], Omega_k of size dims[k] x ell[j] drawn for sketch m (the same
+ * factors krp_hosvd uses for mode m).  The Khatri-Rao product is never formed.
+ *   X      device, prod(dims) elements of `dtype`, Kolda order, 16-byte aligned
+ *          for the vectorised path (any alignment of the element type works)
+ *   d      2..8; dims[k] >= 1
+ *   modes  host, nmodes distinct modes in 0..d-1; ell host, 1..64 per mode
+ *   Y      host array of nmodes device pointers; Y[j] is dims[modes[j]] x ell[j]
+ *          column-major of `dtype` */
+int krp_sketch(const void* X, int dtype, int d, const int64_t* dims, int nmodes,
+               const int32_t* modes, const int32_t* ell, const krp_opts* opts, void* const* Y,
+               void* stream);
+
+/* Randomized HOSVD with KRPs (Algorithm 7) and randomized STHOSVD with KRPs
+ * (Algorithm 8).  ell_i = rank[i] + oversample, 1 <= rank[i] <= ell_i <=
+ * min(dims[i], 64).  Fresh factors for every mode; in STHOSVD the factor of
+ * an already compressed mode j has ell_j rows.
+ *   core   device, capacity prod(ell_i) elements of `dtype`; receives the core
+ *          (ell-sized, or rank-sized when opts->truncate) in Kolda order
+ *   Q      host array of d device pointers; Q[i] capacity dims[i] * ell_i;
+ *          receives the orthonormal factor (dims[i] x ell_i or x rank[i])
+ *   core_dims host out (d entries), may be NULL */
+int krp_hosvd(const void* X, int dtype, int d, const int64_t* dims, const int32_t* rank,
+              int32_t oversample, const krp_opts* opts, void* core, void* const* Q,
+              int64_t* core_dims, void* stream);
+int krp_sthosvd(const void* X, int dtype, int d, const int64_t* dims, const int32_t* rank,
+                int32_t oversample, const krp_opts* opts, void* core, void* const* Q,
+                int64_t* core_dims, void* stream);
+
+/* Batched single-pass randomized SVD of block-Hankel matrices (Algorithm 6):
+ * instance b has Markov blocks h_0 .. h_{2 s_b - 2} (each m x n, column-major,
+ * stored consecutively; instances stored one after the other) and block
+ * (a, c) of H_b equal to h_{a+c}; H_b is (m s_b) x (n s_b) and is never formed.
+ * Omega = Omega1 kr Omega2 (s_b x ell_r, n x ell_r), Psi = Psi1 kr Psi2
+ * (s_b x ell_l, m x ell_l), factor ids 0..3, counter word 3 = b.
+ *   s      host, batch entries >= 1;  1 <= r <= ell_r <= min(ell_l, 64);
+ *          ell_l = 0 selects ceil(1.5 ell_r); ell_l <= 64; ell_r <= m s_b
+ *   h      device, sum_b (2 s_b - 1) m n elements of `dtype`
+ *   U      device, sum_b m s_b r elements: U_b (m s_b) x r column-major
+ *   S      device, batch * r elements (descending per instance)
+ *   V      device, sum_b n s_b r elements: V_b (n s_b) x r column-major
+ * Each singular pair is sign-normalised: the entry of largest magnitude of
+ * every column of U_b is positive. */
+int krp_hankel_lowrank(int batch, const int64_t* s, int m, int n, const void* h, int dtype, int r,
+                       int ell_r, int ell_l, const krp_opts* opts, void* U, void* S, void* V,
+                       void* stream);
+
+/* Device workspace a call with the same arguments needs when the caller
+ * provides opts->workspace.  `which`: 0 sketch (rank[] = ell[] per listed
+ * mode, nmodes = d, modes 0..d-1), 1 hosvd, 2 sthosvd.  Returns KRP_OK and
+ * writes *bytes, or KRP_EINVAL. */
+int krp_workspace_size(int which, int dtype, int d, const int64_t* dims, const int32_t* rank,
+                       int32_t oversample, int prec, size_t* bytes);
+int krp_hankel_workspace_size(int batch, const int64_t* s, int m, int n, int r, int ell_r,
+                              int ell_l, size_t* bytes);
+
+/* Test hook of the factor generator: writes the rows x cols factor
+ * (column-major) drawn for (seed, draw, sketch, factor f, instance) in
+ * precision prec: KRP_P_FP64 doubles, KRP_P_FP32 floats, KRP_P_BF16 bf16 bit
+ * patterns, KRP_P_BF16X3 the bf16 hi plane followed by the lo plane. */
+int krp_gaussian(uint64_t seed, uint32_t draw, uint32_t sketch, uint32_t f, uint32_t instance,
+                 int64_t rows, int64_t cols, int prec, void* out, void* stream);
+
+const char* krp_status_string(int status);
+const char* krp_last_error(void); /* thread-local detail of the last failure */
+const char* krp_version(void);
+/* Releases the library-owned workspaces and graphs of all devices. */
+int krp_finalize(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* KRP_H */

@@ -1,0 +1,218 @@
+"""libkrp: Khatri-Rao random projections on AMD MI355X (gfx950).
+
+Thin Python binding of the C ABI in ``include/krp.h``; the functions below
+carry the same names without the ``krp_`` prefix and only marshal torch
+tensors (device memory) and the current HIP stream into the C calls.
+
+Tensor layout: a tensor of logical shape (n_1, ..., n_d) must have Kolda
+(column-major) strides, stride(k) = n_1 ... n_{k-1}; :func:`kolda` makes such
+a copy.  Matrices returned (sketches Y, factors Q, U, V) are column-major
+tensors of shape (rows, cols).
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+
+from . import _capi
+from ._capi import KrpError  # noqa: F401
+
+PREC = {"fp64": _capi.KRP_P_FP64, "fp32": _capi.KRP_P_FP32, "bf16": _capi.KRP_P_BF16,
+        "bf16x3": _capi.KRP_P_BF16X3}
+
+__all__ = ["sketch", "hosvd", "sthosvd", "hankel_lowrank", "gaussian", "kolda", "empty_kolda",
+           "workspace_size", "hankel_workspace_size", "finalize", "version", "KrpError", "PREC"]
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def kolda(x):
+    """Copy of ``x`` with column-major (Kolda) strides and the same shape."""
+    rev = list(reversed(range(x.dim())))
+    return x.permute(*rev).contiguous().permute(*rev)
+
+
+def empty_kolda(shape, dtype, device):
+    torch = _torch()
+    rev = list(reversed(range(len(shape))))
+    return torch.empty(tuple(reversed(shape)), dtype=dtype, device=device).permute(*rev)
+
+
+def _is_kolda(x) -> bool:
+    s = 1
+    for k, n in enumerate(x.shape):
+        if n > 1 and x.stride(k) != s:
+            return False
+        s *= n
+    return True
+
+
+def _dtype_code(x):
+    torch = _torch()
+    if x.dtype == torch.float32:
+        return _capi.KRP_F32
+    if x.dtype == torch.float64:
+        return _capi.KRP_F64
+    raise TypeError(f"unsupported dtype {x.dtype}")
+
+
+def _stream(x):
+    torch = _torch()
+    return ctypes.c_void_p(torch.cuda.current_stream(x.device).cuda_stream)
+
+
+def _opts(prec, seed, draw, truncate=False, graph=True, order=None, workspace=None,
+          status=None, want_err=False):
+    o = _capi.KrpOpts()
+    _capi.lib().krp_opts_default(ctypes.byref(o))
+    o.seed = int(seed)
+    o.draw = int(draw)
+    o.prec = PREC[prec] if isinstance(prec, str) else int(prec)
+    o.truncate = 1 if truncate else 0
+    o.flags = 0 if graph else _capi.KRP_FLAG_NO_GRAPH
+    keep = []
+    if order is not None:
+        arr = _capi.i32_array(order)
+        keep.append(arr)
+        o.order = ctypes.cast(arr, ctypes.POINTER(ctypes.c_int32))
+    if workspace is not None:
+        o.workspace = ctypes.c_void_p(workspace.data_ptr())
+        o.workspace_bytes = workspace.numel() * workspace.element_size()
+    if status is not None:
+        o.status_dev = ctypes.c_void_p(status.data_ptr())
+    err = ctypes.c_double(float("nan"))
+    if want_err:
+        o.rel_err = ctypes.pointer(err)
+        keep.append(err)
+    return o, err, keep
+
+
+def _check_tensor(x):
+    if not x.is_cuda:
+        raise ValueError("tensor must live on a GPU")
+    if not _is_kolda(x):
+        raise ValueError("tensor must have Kolda (column-major) strides; use kolda(x)")
+
+
+def sketch(x, modes, ell, prec="fp32", seed=2507, draw=0, graph=True):
+    """KRP sketches Y_j = X_(m_j) (KRP of the other factors); krp_sketch."""
+    torch = _torch()
+    _check_tensor(x)
+    modes = [int(m) for m in modes]
+    ell = [int(v) for v in ell] if hasattr(ell, "__len__") else [int(ell)] * len(modes)
+    ys = [torch.empty((l, x.shape[m]), dtype=x.dtype, device=x.device).t() for m, l in zip(modes, ell)]
+    o, _, keep = _opts(prec, seed, draw, graph=graph)
+    rc = _capi.lib().krp_sketch(ctypes.c_void_p(x.data_ptr()), _dtype_code(x), x.dim(),
+                                _capi.i64_array(x.shape), len(modes), _capi.i32_array(modes),
+                                _capi.i32_array(ell), ctypes.byref(o),
+                                _capi.ptr_array([y.data_ptr() for y in ys]), _stream(x))
+    _capi.check(rc)
+    return ys
+
+
+def _tucker(fn, x, ranks, oversample, prec, seed, draw, truncate, rel_err, graph, order,
+            workspace, status):
+    _check_tensor(x)
+    d = x.dim()
+    ranks = [int(r) for r in ranks]
+    ells = [r + int(oversample) for r in ranks]
+    core = empty_kolda(ells, x.dtype, x.device)
+    qs = [_torch().empty((l, n), dtype=x.dtype, device=x.device).t() for n, l in zip(x.shape, ells)]
+    o, err, keep = _opts(prec, seed, draw, truncate, graph, order, workspace, status, rel_err)
+    cdims = (ctypes.c_int64 * d)()
+    rc = fn(ctypes.c_void_p(x.data_ptr()), _dtype_code(x), d, _capi.i64_array(x.shape),
+            _capi.i32_array(ranks), int(oversample), ctypes.byref(o), ctypes.c_void_p(core.data_ptr()),
+            _capi.ptr_array([q.data_ptr() for q in qs]), cdims, _stream(x))
+    _capi.check(rc)
+    out_dims = [int(v) for v in cdims]
+    if truncate:
+        n = math.prod(out_dims)
+        core = core.permute(*reversed(range(d))).reshape(-1)[:n]
+        core = core.reshape(tuple(reversed(out_dims))).permute(*reversed(range(d)))
+        qs = [q.t().reshape(-1)[: x.shape[k] * ranks[k]].reshape(ranks[k], x.shape[k]).t()
+              for k, q in enumerate(qs)]
+    return core, qs, (err.value if rel_err else None)
+
+
+def hosvd(x, ranks, oversample, prec="fp32", seed=2507, draw=0, truncate=False, rel_err=False,
+          graph=True, workspace=None, status=None):
+    """Randomized HOSVD with KRPs (Algorithm 7); krp_hosvd.  Returns (core, [Q_i], rel_err)."""
+    return _tucker(_capi.lib().krp_hosvd, x, ranks, oversample, prec, seed, draw, truncate, rel_err,
+                   graph, None, workspace, status)
+
+
+def sthosvd(x, ranks, oversample, prec="fp32", seed=2507, draw=0, truncate=False, rel_err=False,
+            graph=True, order=None, workspace=None, status=None):
+    """Randomized STHOSVD with KRPs (Algorithm 8); krp_sthosvd.  Returns (core, [Q_i], rel_err)."""
+    return _tucker(_capi.lib().krp_sthosvd, x, ranks, oversample, prec, seed, draw, truncate, rel_err,
+                   graph, order, workspace, status)
+
+
+def hankel_lowrank(s, h, m, n, r, ell_r, ell_l=0, prec="fp32", seed=2507, draw=0, graph=True):
+    """Batched single-pass block-Hankel SVD (Algorithm 6); krp_hankel_lowrank.
+
+    ``s``: block counts per instance; ``h``: packed Markov blocks (1-D device
+    tensor).  Returns packed (U, S, V) 1-D tensors."""
+    torch = _torch()
+    s = [int(v) for v in s]
+    if not h.is_cuda or not h.is_contiguous():
+        raise ValueError("h must be a contiguous GPU tensor")
+    U = torch.empty(sum(m * v * r for v in s), dtype=h.dtype, device=h.device)
+    S = torch.empty(len(s) * r, dtype=h.dtype, device=h.device)
+    V = torch.empty(sum(n * v * r for v in s), dtype=h.dtype, device=h.device)
+    o, _, keep = _opts(prec, seed, draw, graph=graph)
+    rc = _capi.lib().krp_hankel_lowrank(len(s), _capi.i64_array(s), int(m), int(n),
+                                        ctypes.c_void_p(h.data_ptr()), _dtype_code(h), int(r), int(ell_r),
+                                        int(ell_l), ctypes.byref(o), ctypes.c_void_p(U.data_ptr()),
+                                        ctypes.c_void_p(S.data_ptr()), ctypes.c_void_p(V.data_ptr()),
+                                        _stream(h))
+    _capi.check(rc)
+    return U, S, V
+
+
+def gaussian(seed, draw, sketch_id, f, instance, rows, cols, prec="fp64", device="cuda"):
+    """Factor entries of the RNG spec drawn on the GPU (krp_gaussian test hook)."""
+    torch = _torch()
+    p = PREC[prec] if isinstance(prec, str) else int(prec)
+    n = rows * cols
+    if p == _capi.KRP_P_FP64:
+        out = torch.empty(n, dtype=torch.float64, device=device)
+    elif p == _capi.KRP_P_FP32:
+        out = torch.empty(n, dtype=torch.float32, device=device)
+    elif p == _capi.KRP_P_BF16:
+        out = torch.empty(n, dtype=torch.int16, device=device)
+    else:
+        out = torch.empty(2 * n, dtype=torch.int16, device=device)
+    rc = _capi.lib().krp_gaussian(int(seed), int(draw), int(sketch_id), int(f), int(instance), int(rows),
+                                  int(cols), p, ctypes.c_void_p(out.data_ptr()),
+                                  ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
+    _capi.check(rc)
+    return out
+
+
+def workspace_size(which, dtype, dims, ranks, oversample, prec):
+    nb = ctypes.c_size_t(0)
+    rc = _capi.lib().krp_workspace_size(int(which), int(dtype), len(dims), _capi.i64_array(dims),
+                                        _capi.i32_array(ranks), int(oversample),
+                                        PREC[prec] if isinstance(prec, str) else int(prec), ctypes.byref(nb))
+    _capi.check(rc)
+    return nb.value
+
+
+def hankel_workspace_size(s, m, n, r, ell_r, ell_l=0):
+    nb = ctypes.c_size_t(0)
+    rc = _capi.lib().krp_hankel_workspace_size(len(s), _capi.i64_array(s), int(m), int(n), int(r),
+                                               int(ell_r), int(ell_l), ctypes.byref(nb))
+    _capi.check(rc)
+    return nb.value
+
+
+def finalize():
+    _capi.check(_capi.lib().krp_finalize())
+
+
+def version() -> str:
+    return _capi.lib().krp_version().decode()

@@ -1,0 +1,36 @@
+// Host-side helpers shared by the libkrp drivers (capi.cpp, tucker.cpp,
+// hankel_driver.cpp).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <functional>
+#include <string>
+
+#include "../../include/krp.h"
+
+namespace krp {
+
+// Records `msg` as the thread's last error and returns `code`.
+int set_error(int code, const char* fmt, ...);
+int hip_fail(hipError_t e, const char* what);
+
+// Device workspace of at least `need` bytes: the caller's (opts->workspace)
+// or the library-owned buffer of (current device, stream).  Must be called
+// before run_maybe_graph.
+int acquire_workspace(const krp_opts* o, size_t need, hipStream_t st, char** out);
+
+// Runs body(stream) directly, or captures it once into a HIP graph cached
+// under `key` and launches the graph on `st`.  `body` must only enqueue work.
+int run_maybe_graph(const std::string& key, bool use_graph, hipStream_t st,
+                    const std::function<int(hipStream_t)>& body);
+
+// Copies the status word to the host (synchronising `st`) and maps its bits
+// to a return code.
+int finish_status(const int* status_ws, hipStream_t st);
+
+std::string ptr_key(const void* p);
+int release_all();
+
+inline size_t align_up(size_t v, size_t a = 256) { return (v + a - 1) / a * a; }
+
+}  // namespace krp

@@ -1,0 +1,100 @@
+// Host-side launch interfaces of the libkrp HIP kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace krp {
+
+constexpr int kMaxDims = 8;
+
+// Tiling of one mode sketch (chosen by the planner or the autotuner).
+struct SketchTile {
+  int mt = 4;         // 16-row M tiles per wave
+  int wm = 0;         // waves along the rows (0: derived from the row count)
+  int wo = 0;         // waves splitting the outer iterations (0: derived)
+  int64_t o_per_wg = 0;  // outer iterations per workgroup (0: derived)
+  int target_wgs = 512;  // workgroups aimed for when deriving o_per_wg
+};
+
+// Problem description of a single-mode MTTKRP sketch
+//   Y[a, c] = sum_{all i_k, k != mode; i_mode = a} x[i] prod_{k != mode} Omega_k[i_k, c]
+// for a dense tensor in Kolda order (mode 0 fastest).
+struct SketchProblem {
+  const void* x = nullptr;
+  int x_is_double = 0;
+  int d = 0;
+  int64_t dims[kMaxDims] = {0};
+  int mode = 0;
+  int ell = 0;
+  int prec = 0;               // Prec
+  uint64_t seed = 0;
+  uint32_t draw = 0;
+  uint32_t sketch_id = 0;     // counter field "sketch" (normally == mode)
+};
+
+struct SketchPlan {
+  int fmode, n_out;
+  int64_t n_rows, s_row, n_f, s_f;
+  int64_t o_size[kMaxDims], o_stride[kMaxDims];
+  int o_fid[kMaxDims];
+  int64_t o_total, o_per_wg;
+  int o_ranges, f_blocks, row_blocks, col_chunks;
+  int mt, nt, wm, wo, kvec;
+  int cpad, nparts;
+  int lds_rows;           // factor-table rows the LDS allocation holds
+  size_t lds_bytes;
+  size_t partial_bytes;   // bytes of the partial-sum buffer
+};
+
+SketchPlan plan_sketch(const SketchProblem& pb, const SketchTile& tile);
+
+// Launches the sketch of one mode: partial sums into `partial` (workspace of
+// plan.partial_bytes), then the deterministic reduction into y64 (fp64,
+// n_rows x ell column-major) and, if y_out is not null, into y_out in the
+// storage type (double when out_is_double).
+hipError_t launch_sketch(const SketchProblem& pb, const SketchPlan& plan, void* partial,
+                         double* y64, void* y_out, int out_is_double, hipStream_t st);
+
+// Fills out (rows x cols, column-major) with the factor entries of the RNG
+// spec in precision prec (0 fp64, 1 fp32, 2 bf16 bits, 3 bf16 hi plane then
+// lo plane).
+hipError_t launch_gaussian(uint64_t seed, uint64_t w2, uint64_t instance, int64_t rows,
+                           int64_t cols, int prec, void* out, hipStream_t st);
+
+// Batched CholeskyQR2 of column-major fp64 matrices Y_b (n_b x ell), with a
+// shifted CholeskyQR3 fallback.  q64 receives Q_b in fp64 (may alias y64),
+// q_out (optional) in the storage type.  offsets[b] is the element offset of
+// matrix b (device array, or null for a single matrix at offset 0), nrows[b]
+// its row count (device array, or null: all have n rows).
+hipError_t launch_cholqr(int batch, int64_t n, int ell, const double* y64, double* q64,
+                         void* q_out, int out_is_double, const int64_t* offsets,
+                         const int64_t* nrows, int* status, hipStream_t st);
+
+// TTM G_new = G x_mode Q^T for a tensor in Kolda order with current sizes
+// dims (dims[mode] = n rows of Q), Q (n x ell, fp64 column-major).
+struct TtmProblem {
+  const void* g = nullptr;
+  int g_is_double = 0;
+  void* out = nullptr;
+  int out_is_double = 0;
+  int d = 0;
+  int64_t dims[kMaxDims] = {0};
+  int mode = 0;
+  int ell = 0;
+  int prec = 0;
+  const double* q64 = nullptr;
+};
+hipError_t launch_ttm(const TtmProblem& pb, void* qbuf, hipStream_t st);
+size_t ttm_qbuf_bytes(int64_t n, int ell);
+
+// Casts between storage types (count elements).
+hipError_t launch_cast(const void* in, int in_is_double, void* out, int out_is_double,
+                       int64_t count, hipStream_t st);
+// Sum of squares of a storage-type array into *acc (fp64, cleared first).
+hipError_t launch_sumsq(const void* x, int is_double, int64_t count, double* acc,
+                        double* scratch, int scratch_len, hipStream_t st);
+// Fills count ints with value (graph-safe replacement for memset).
+hipError_t launch_fill_int(int* p, int value, int64_t count, hipStream_t st);
+
+}  // namespace krp

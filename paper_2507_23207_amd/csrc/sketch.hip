@@ -1,0 +1,465 @@
+// KRP sketch of one mode unfolding of a dense tensor (the MTTKRP of
+// Algorithm 7, step 3 and Algorithm 8, step 4):
+//   Y_(i) = X_(i) (Omega_d kr ... kr Omega_{i+1} kr Omega_{i-1} kr ... kr Omega_1).
+// The Khatri-Rao product is never formed.  The tensor is viewed as
+//   x[i_f, a, o]   (a = i_mode, f = fastest other mode, o = remaining modes)
+// and every column of the KRP factorises as Omega_f[i_f, c] * W[o, c] with
+// W[o, c] = prod_{k in o} Omega_k[o_k, c].  A workgroup owns a 32-wide block
+// of i_f, a range of o and all (or a block of) rows a; it draws the factor rows
+// it needs into LDS with the counter-based generator, then streams its slab of
+// X once: each 16-row x 32-deep slice of X is an MFMA A fragment, the matching
+// KRP weights (Omega_f slice times W[o, :]) the B fragment.  Per-workgroup
+// partial sums are reduced deterministically (fixed order, fp64) by a second
+// kernel.
+#include "device_common.h"
+#include "kernels.h"
+#include "philox.h"
+
+#include <algorithm>
+
+namespace krp {
+
+namespace {
+
+struct SketchArgs {
+  const void* x;
+  void* partial;
+  int64_t n_rows, s_row, n_f, s_f;
+  int64_t o_size[kMaxDims], o_stride[kMaxDims], o_period[kMaxDims];
+  int o_fid[kMaxDims];
+  int n_out;
+  int64_t o_total, o_per_wg;
+  int f_blocks, ell, nparts, wm, wo, rows_per_wg, fid_f, lds_rows;
+  uint64_t seed, w2_base;
+};
+
+// Reduction slot -> k offset inside the 32-wide block.  With vector loads
+// (the block is contiguous in memory) lane group g reads 16-byte pieces so
+// that the four groups of a row cover 64 contiguous bytes per instruction.
+template <typename Tin, bool KVEC>
+__device__ __forceinline__ int kmap(int g, int j) {
+  if constexpr (KVEC) {
+    constexpr int V = 16 / sizeof(Tin);
+    return V * g + 4 * V * (j / V) + (j % V);
+  } else {
+    return 8 * g + j;
+  }
+}
+
+template <typename Tin, int P, bool KVEC, int MT, int NT>
+__global__ __launch_bounds__(512) void sketch_kernel(SketchArgs a) {
+  using Pol = Policy<P>;
+  using T = typename Pol::T;
+  using AccT = typename Pol::AccT;
+  constexpr int CP = 16 * NT;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T* tab = reinterpret_cast<T*>(smem_raw);
+
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int w_m = wave % a.wm;
+  const int w_o = wave / a.wm;
+  const int kg = blockIdx.x;
+  const int fb = kg % a.f_blocks;
+  const int64_t orange = kg / a.f_blocks;
+  const int64_t f0 = (int64_t)fb * 32;
+  const int64_t a0 = (int64_t)blockIdx.y * a.rows_per_wg + (int64_t)w_m * 16 * MT;
+  const int col0 = blockIdx.z * CP;
+  const int64_t o_begin = orange * a.o_per_wg;
+  const int64_t o_end = min(o_begin + a.o_per_wg, a.o_total);
+
+  // Rows of each outer-mode factor that this workgroup's o range touches.
+  int64_t lo[kMaxDims];
+  int toff[kMaxDims];
+  int rows_total = 32;
+#pragma unroll
+  for (int k = 0; k < kMaxDims; ++k) {
+    lo[k] = 0;
+    toff[k] = 0;
+    if (k < a.n_out) {
+      // The o range visits digits lo, lo+1, ... (cyclically, mod o_size) of
+      // this mode: at most q1 - q0 + 1 distinct values.
+      const int64_t q0 = o_begin / a.o_period[k], q1 = (o_end - 1) / a.o_period[k];
+      const int64_t cnt = min(a.o_size[k], q1 - q0 + 1);
+      lo[k] = cnt == a.o_size[k] ? 0 : q0 % a.o_size[k];
+      toff[k] = rows_total;
+      rows_total += (int)cnt;
+    }
+  }
+
+  AccT* part = reinterpret_cast<AccT*>(a.partial) +
+               ((int64_t)blockIdx.z * a.nparts + (int64_t)kg * a.wo + w_o) * a.n_rows * CP;
+  const int n = lane & 15, g = lane >> 4;
+  // The host sized the LDS for lds_rows table rows.  A plan that undercounts
+  // would be a planner bug: the workgroup then poisons its partial sums with
+  // NaN (reported as non-finite by the QR) instead of overrunning the LDS.
+  if (rows_total > a.lds_rows) {
+#pragma unroll
+    for (int m = 0; m < MT; ++m)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t row = a0 + 16 * m + Pol::out_row(g, r);
+        if (row < a.n_rows) {
+#pragma unroll
+          for (int t = 0; t < NT; ++t) part[row * CP + 16 * t + n] = (AccT)__builtin_nan("");
+        }
+      }
+    return;
+  }
+
+  // Draw the factor rows (fp64 Gaussians rounded to the working precision).
+  for (int e = threadIdx.x; e < rows_total * CP; e += blockDim.x) {
+    const int r = e / CP, c = e - (e / CP) * CP;
+    const int gc = col0 + c;
+    T v = (T)0;
+    if (gc < a.ell) {
+      if (r < 32) {
+        const int64_t row = f0 + r;
+        if (row < a.n_f) v = factor_value<P>(gauss_entry(a.seed, a.w2_base | (uint64_t)a.fid_f, 0, row, gc));
+      } else {
+        int k = 0;
+#pragma unroll
+        for (int kk = 1; kk < kMaxDims; ++kk)
+          if (kk < a.n_out && r >= toff[kk]) k = kk;
+        const int64_t row = (lo[k] + (r - toff[k])) % a.o_size[k];
+        v = factor_value<P>(gauss_entry(a.seed, a.w2_base | (uint64_t)a.o_fid[k], 0, row, gc));
+      }
+    }
+    tab[e] = v;
+  }
+  __syncthreads();
+
+  T wf[NT][8];
+#pragma unroll
+  for (int t = 0; t < NT; ++t)
+#pragma unroll
+    for (int j = 0; j < 8; ++j) wf[t][j] = tab[kmap<Tin, KVEC>(g, j) * CP + 16 * t + n];
+
+  typename Pol::Acc acc[MT][NT];
+#pragma unroll
+  for (int m = 0; m < MT; ++m)
+#pragma unroll
+    for (int t = 0; t < NT; ++t) acc[m][t] = Pol::zero();
+
+  const Tin* X = reinterpret_cast<const Tin*>(a.x);
+  for (int64_t o = o_begin + w_o; o < o_end; o += a.wo) {
+    int64_t off = 0;
+    T w[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) w[t] = (T)1;
+    int64_t rem = o;
+#pragma unroll
+    for (int k = 0; k < kMaxDims; ++k) {
+      if (k < a.n_out) {
+        const int64_t dk = rem % a.o_size[k];
+        rem /= a.o_size[k];
+        off += dk * a.o_stride[k];
+        const int rr = toff[k] + (int)((dk - lo[k] + a.o_size[k]) % a.o_size[k]);
+#pragma unroll
+        for (int t = 0; t < NT; ++t) w[t] = w[t] * tab[rr * CP + 16 * t + n];
+      }
+    }
+
+    // A fragments (all M tiles first, so their loads are in flight together).
+    T av[MT][8];
+#pragma unroll
+    for (int m = 0; m < MT; ++m) {
+      const int64_t row = a0 + 16 * m + n;
+      const bool rv = row < a.n_rows;
+      const int64_t base = off + row * a.s_row + f0 * a.s_f;
+      if constexpr (KVEC) {
+        if constexpr (sizeof(Tin) == 4) {
+#pragma unroll
+          for (int h = 0; h < 2; ++h) {
+            const int kk = 4 * g + 16 * h;
+            float4 q = make_float4(0.f, 0.f, 0.f, 0.f);
+            if (rv && f0 + kk < a.n_f) q = *reinterpret_cast<const float4*>(X + base + kk);
+            av[m][4 * h + 0] = (T)q.x;
+            av[m][4 * h + 1] = (T)q.y;
+            av[m][4 * h + 2] = (T)q.z;
+            av[m][4 * h + 3] = (T)q.w;
+          }
+        } else {
+#pragma unroll
+          for (int h = 0; h < 4; ++h) {
+            const int kk = 2 * g + 8 * h;
+            double2 q = make_double2(0.0, 0.0);
+            if (rv && f0 + kk < a.n_f) q = *reinterpret_cast<const double2*>(X + base + kk);
+            av[m][2 * h + 0] = (T)q.x;
+            av[m][2 * h + 1] = (T)q.y;
+          }
+        }
+      } else {
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+          const int kk = 8 * g + j;
+          Tin v = (Tin)0;
+          if (rv && f0 + kk < a.n_f) v = X[base + (int64_t)kk * a.s_f];
+          av[m][j] = (T)v;
+        }
+      }
+    }
+
+    typename Pol::Frag bf[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      T v[8];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) v[j] = wf[t][j] * w[t];
+      bf[t] = Pol::make(v);
+    }
+#pragma unroll
+    for (int m = 0; m < MT; ++m) {
+      const typename Pol::Frag af = Pol::make(av[m]);
+#pragma unroll
+      for (int t = 0; t < NT; ++t) Pol::mma(acc[m][t], af, bf[t]);
+    }
+  }
+
+#pragma unroll
+  for (int m = 0; m < MT; ++m)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int64_t row = a0 + 16 * m + Pol::out_row(g, r);
+      if (row < a.n_rows) {
+#pragma unroll
+        for (int t = 0; t < NT; ++t) part[row * CP + 16 * t + n] = acc[m][t][r];
+      }
+    }
+}
+
+// Y[a, c] = sum_p partial[chunk(c)][p][a][c mod CP], summed in fp64 in the
+// fixed order p = 0, 1, ...
+template <typename AccT>
+__global__ void sketch_reduce_kernel(const AccT* __restrict__ partial, int nparts, int64_t n_rows,
+                                     int ell, int cp, double* __restrict__ y64, void* yout,
+                                     int out_double) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= n_rows * ell) return;
+  const int64_t a = idx / ell;
+  const int c = (int)(idx - a * ell);
+  const int z = c / cp, cc = c - z * cp;
+  const int64_t stride = n_rows * cp;
+  const AccT* p = partial + (int64_t)z * nparts * stride + a * cp + cc;
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+  int q = 0;
+  for (; q + 4 <= nparts; q += 4) {
+    s0 += (double)p[(int64_t)(q + 0) * stride];
+    s1 += (double)p[(int64_t)(q + 1) * stride];
+    s2 += (double)p[(int64_t)(q + 2) * stride];
+    s3 += (double)p[(int64_t)(q + 3) * stride];
+  }
+  for (; q < nparts; ++q) s0 += (double)p[(int64_t)q * stride];
+  const double s = (s0 + s1) + (s2 + s3);
+  const int64_t o = a + n_rows * c;
+  if (y64) y64[o] = s;
+  if (yout) {
+    if (out_double)
+      reinterpret_cast<double*>(yout)[o] = s;
+    else
+      reinterpret_cast<float*>(yout)[o] = (float)s;
+  }
+}
+
+__global__ void gaussian_kernel(uint64_t seed, uint64_t w2, uint64_t instance, int64_t rows,
+                                int64_t cols, int prec, void* out) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= rows * cols) return;
+  const int64_t r = idx % rows, c = idx / rows;
+  const double gv = gauss_entry(seed, w2, instance, (uint64_t)r, (uint64_t)c);
+  if (prec == kFP64) {
+    reinterpret_cast<double*>(out)[idx] = gv;
+  } else if (prec == kFP32) {
+    reinterpret_cast<float*>(out)[idx] = (float)gv;
+  } else {
+    const float x = (float)gv;
+    const __bf16 h = (__bf16)x;
+    reinterpret_cast<__bf16*>(out)[idx] = h;
+    if (prec == kBF16X3) reinterpret_cast<__bf16*>(out)[rows * cols + idx] = (__bf16)(x - (float)h);
+  }
+}
+
+template <typename Tin, int P, bool KVEC, int MT, int NT>
+hipError_t launch_inst(const SketchArgs& args, dim3 grid, int threads, size_t lds, hipStream_t st) {
+  auto kern = sketch_kernel<Tin, P, KVEC, MT, NT>;
+  if (lds > 65536) {
+    hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(kern, grid, dim3(threads), lds, st, args);
+  return hipGetLastError();
+}
+
+template <typename Tin, int P, bool KVEC, int MT>
+hipError_t dispatch_nt(int nt, const SketchArgs& args, dim3 grid, int threads, size_t lds, hipStream_t st) {
+  switch (nt) {
+    case 1: return launch_inst<Tin, P, KVEC, MT, 1>(args, grid, threads, lds, st);
+    case 2: return launch_inst<Tin, P, KVEC, MT, 2>(args, grid, threads, lds, st);
+    case 3: return launch_inst<Tin, P, KVEC, MT, 3>(args, grid, threads, lds, st);
+    default: return launch_inst<Tin, P, KVEC, MT, 4>(args, grid, threads, lds, st);
+  }
+}
+
+template <typename Tin, int P, bool KVEC>
+hipError_t dispatch_mt(int mt, int nt, const SketchArgs& args, dim3 grid, int threads, size_t lds,
+                       hipStream_t st) {
+  switch (mt) {
+    case 1: return dispatch_nt<Tin, P, KVEC, 1>(nt, args, grid, threads, lds, st);
+    case 2: return dispatch_nt<Tin, P, KVEC, 2>(nt, args, grid, threads, lds, st);
+    default: return dispatch_nt<Tin, P, KVEC, 4>(nt, args, grid, threads, lds, st);
+  }
+}
+
+template <typename Tin, int P>
+hipError_t dispatch_kvec(int kvec, int mt, int nt, const SketchArgs& args, dim3 grid, int threads,
+                         size_t lds, hipStream_t st) {
+  if (kvec) return dispatch_mt<Tin, P, true>(mt, nt, args, grid, threads, lds, st);
+  return dispatch_mt<Tin, P, false>(mt, nt, args, grid, threads, lds, st);
+}
+
+}  // namespace
+
+SketchPlan plan_sketch(const SketchProblem& pb, const SketchTile& tile) {
+  SketchPlan p{};
+  int64_t stride[kMaxDims];
+  int64_t s = 1;
+  for (int k = 0; k < pb.d; ++k) {
+    stride[k] = s;
+    s *= pb.dims[k];
+  }
+  const int i = pb.mode;
+  p.fmode = (i == 0) ? 1 : 0;
+  p.n_rows = pb.dims[i];
+  p.s_row = stride[i];
+  p.n_f = pb.dims[p.fmode];
+  p.s_f = stride[p.fmode];
+  p.n_out = 0;
+  p.o_total = 1;
+  for (int k = 0; k < pb.d; ++k) {
+    if (k == i || k == p.fmode) continue;
+    p.o_size[p.n_out] = pb.dims[k];
+    p.o_stride[p.n_out] = stride[k];
+    p.o_fid[p.n_out] = k;
+    p.o_total *= pb.dims[k];
+    ++p.n_out;
+  }
+  const bool fp64 = pb.prec == kFP64;
+  const size_t tsz = fp64 ? 8 : 4;
+  p.nt = pb.ell >= 64 ? 4 : (pb.ell + 15) / 16;
+  p.cpad = 16 * p.nt;
+  p.col_chunks = (pb.ell + p.cpad - 1) / p.cpad;
+  int mt = tile.mt;
+  if (mt != 1 && mt != 2) mt = 4;
+  while (mt > 1 && 16 * (mt / 2) >= p.n_rows) mt /= 2;
+  if (fp64 && mt > 2 && p.nt >= 3) mt = 2;  // register budget of fp64 fragments
+  p.mt = mt;
+  const int64_t wave_rows = 16 * mt;
+  int wm = tile.wm > 0 ? tile.wm : (int)std::min<int64_t>(8, (p.n_rows + wave_rows - 1) / wave_rows);
+  p.wm = std::max(1, std::min(8, wm));
+  p.row_blocks = (int)((p.n_rows + wave_rows * p.wm - 1) / (wave_rows * p.wm));
+  int wo = tile.wo > 0 ? tile.wo : std::max(1, 8 / p.wm);
+  while (p.wm * wo > 8) --wo;
+  p.wo = std::max(1, wo);
+  p.f_blocks = (int)((p.n_f + 31) / 32);
+  p.kvec = (i != 0) && (p.n_f % (int64_t)(16 / (pb.x_is_double ? 8 : 4)) == 0);
+
+  int64_t o_per = tile.o_per_wg;
+  if (o_per <= 0) {
+    const int64_t per_o = (int64_t)p.f_blocks * p.row_blocks * p.col_chunks;
+    int64_t ranges = std::max<int64_t>(1, tile.target_wgs / std::max<int64_t>(1, per_o));
+    ranges = std::min(ranges, p.o_total);
+    o_per = (p.o_total + ranges - 1) / ranges;
+  }
+  o_per = std::max<int64_t>(1, std::min(o_per, p.o_total));
+  // Keep the LDS factor tables under 64 KiB.
+  for (;;) {
+    int64_t rows = 32, period = 1;
+    for (int k = 0; k < p.n_out; ++k) {
+      rows += std::min<int64_t>(p.o_size[k], (o_per + period - 1) / period + 1);
+      period *= p.o_size[k];
+    }
+    p.lds_rows = (int)rows;
+    p.lds_bytes = (size_t)rows * p.cpad * tsz;
+    if (p.lds_bytes <= 65536 || o_per == 1) break;
+    o_per = (o_per + 1) / 2;
+  }
+  p.o_per_wg = o_per;
+  p.o_ranges = (int)((p.o_total + o_per - 1) / o_per);
+  p.nparts = p.f_blocks * p.o_ranges * p.wo;
+  p.partial_bytes = (size_t)p.col_chunks * p.nparts * p.n_rows * p.cpad * tsz;
+  return p;
+}
+
+hipError_t launch_sketch(const SketchProblem& pb, const SketchPlan& p, void* partial, double* y64,
+                         void* y_out, int out_is_double, hipStream_t st) {
+  SketchArgs a{};
+  a.x = pb.x;
+  a.partial = partial;
+  a.n_rows = p.n_rows;
+  a.s_row = p.s_row;
+  a.n_f = p.n_f;
+  a.s_f = p.s_f;
+  int64_t period = 1;
+  for (int k = 0; k < kMaxDims; ++k) {
+    a.o_size[k] = k < p.n_out ? p.o_size[k] : 1;
+    a.o_stride[k] = k < p.n_out ? p.o_stride[k] : 0;
+    a.o_fid[k] = k < p.n_out ? p.o_fid[k] : 0;
+    a.o_period[k] = period;
+    if (k < p.n_out) period *= p.o_size[k];
+  }
+  a.n_out = p.n_out;
+  a.o_total = p.o_total;
+  a.o_per_wg = p.o_per_wg;
+  a.f_blocks = p.f_blocks;
+  a.ell = pb.ell;
+  a.nparts = p.nparts;
+  a.wm = p.wm;
+  a.wo = p.wo;
+  a.rows_per_wg = 16 * p.mt * p.wm;
+  a.fid_f = p.fmode;
+  a.lds_rows = p.lds_rows;
+  a.seed = pb.seed;
+  a.w2_base = counter_word2(pb.draw, pb.sketch_id, 0);
+
+  // Vector loads need 16-byte aligned rows; misaligned views take the scalar path.
+  const int kvec = p.kvec && ((reinterpret_cast<uintptr_t>(pb.x) & 15) == 0);
+  const dim3 grid((unsigned)(p.f_blocks * p.o_ranges), (unsigned)p.row_blocks, (unsigned)p.col_chunks);
+  const int threads = 64 * p.wm * p.wo;
+  hipError_t e;
+  if (pb.x_is_double) {
+    if (pb.prec != kFP64) return hipErrorInvalidValue;
+    e = dispatch_kvec<double, kFP64>(kvec, p.mt, p.nt, a, grid, threads, p.lds_bytes, st);
+  } else {
+    switch (pb.prec) {
+      case kFP64: e = dispatch_kvec<float, kFP64>(kvec, p.mt, p.nt, a, grid, threads, p.lds_bytes, st); break;
+      case kFP32: e = dispatch_kvec<float, kFP32>(kvec, p.mt, p.nt, a, grid, threads, p.lds_bytes, st); break;
+      case kBF16: e = dispatch_kvec<float, kBF16>(kvec, p.mt, p.nt, a, grid, threads, p.lds_bytes, st); break;
+      default: e = dispatch_kvec<float, kBF16X3>(kvec, p.mt, p.nt, a, grid, threads, p.lds_bytes, st); break;
+    }
+  }
+  if (e != hipSuccess) return e;
+  const int64_t nout = p.n_rows * pb.ell;
+  const int rt = 256;
+  const unsigned rg = (unsigned)((nout + rt - 1) / rt);
+  if (pb.prec == kFP64)
+    hipLaunchKernelGGL(sketch_reduce_kernel<double>, dim3(rg), dim3(rt), 0, st,
+                       reinterpret_cast<const double*>(partial), p.nparts, p.n_rows, pb.ell, p.cpad,
+                       y64, y_out, out_is_double);
+  else
+    hipLaunchKernelGGL(sketch_reduce_kernel<float>, dim3(rg), dim3(rt), 0, st,
+                       reinterpret_cast<const float*>(partial), p.nparts, p.n_rows, pb.ell, p.cpad,
+                       y64, y_out, out_is_double);
+  return hipGetLastError();
+}
+
+hipError_t launch_gaussian(uint64_t seed, uint64_t w2, uint64_t instance, int64_t rows, int64_t cols,
+                           int prec, void* out, hipStream_t st) {
+  const int64_t n = rows * cols;
+  if (n == 0) return hipSuccess;
+  const int t = 256;
+  hipLaunchKernelGGL(gaussian_kernel, dim3((unsigned)((n + t - 1) / t)), dim3(t), 0, st, seed, w2,
+                     instance, rows, cols, prec, out);
+  return hipGetLastError();
+}
+
+}  // namespace krp

@@ -1,0 +1,269 @@
+// Tensor-times-matrix G_new = G x_i Q^T (Algorithm 7, step 6; Algorithm 8,
+// step 6): G_new_(i) = Q^T G_(i) for a tensor in Kolda order and an n x l
+// orthonormal Q.  The tensor is viewed as g[p, a, q] (p = modes before i,
+// a = i_i, q = modes after i); G_new[p, c, q] = sum_a g[p, a, q] Q[a, c].
+//
+// Mode 0 (p empty): MFMA tile D[q][c] = sum_a G[a, q] Q[a, c]; the reduction
+// runs along the contiguous index a (vector loads), results are written row
+// by row of the l x (rest) output.
+// Other modes: D[c][p] = sum_a Q[a, c] g[p, a, q]; 16 consecutive p form the
+// coalesced B operand and the output columns.
+// The workgroup walks the reduction index in 32-wide slices in lockstep; each
+// slice of Q is staged once in LDS (double-buffered) for all its waves.
+#include "device_common.h"
+#include "kernels.h"
+
+#include <algorithm>
+#include <type_traits>
+
+namespace krp {
+
+namespace {
+
+constexpr int kTtmWaves = 8;
+constexpr int kSlicePitch = 36;  // 32 reduction slots + padding (elements)
+
+struct TtmArgs {
+  const void* g;
+  void* out;
+  const double* q;
+  int64_t P, n, Q;  // g[p, a, q] sizes
+  int ell;
+  int64_t items;
+  int p_groups;     // non-mode-0: p groups per q
+};
+
+template <typename Tin, bool KVEC>
+__device__ __forceinline__ int tkmap(int g, int j) {
+  if constexpr (KVEC) {
+    constexpr int V = 16 / sizeof(Tin);
+    return V * g + 4 * V * (j / V) + (j % V);
+  } else {
+    return 8 * g + j;
+  }
+}
+
+template <typename Tin, int P, bool MODE0, bool KVEC, int MT, int NT>
+__global__ __launch_bounds__(64 * kTtmWaves) void ttm_kernel(TtmArgs a) {
+  using Pol = Policy<P>;
+  using T = typename Pol::T;
+  using Tout = typename std::conditional<P == kFP64, double, float>::type;
+  constexpr int CQ = 16 * (MODE0 ? NT : MT);  // padded columns of Q
+  __shared__ __align__(16) T slice[2][CQ * kSlicePitch];
+
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int n = lane & 15, g = lane >> 4;
+  const int64_t item = (int64_t)blockIdx.x * kTtmWaves + wave;
+  const bool active = item < a.items;
+  int64_t q0 = 0, p0 = 0, qq = 0;
+  if constexpr (MODE0) {
+    q0 = item * (16 * MT);
+  } else {
+    qq = item / a.p_groups;
+    p0 = (item % a.p_groups) * (16 * NT);
+  }
+  const Tin* G = reinterpret_cast<const Tin*>(a.g);
+
+  typename Pol::Acc acc[MT][NT];
+#pragma unroll
+  for (int m = 0; m < MT; ++m)
+#pragma unroll
+    for (int t = 0; t < NT; ++t) acc[m][t] = Pol::zero();
+
+  auto stage = [&](int buf, int64_t k0) {
+    for (int e = threadIdx.x; e < CQ * 32; e += 64 * kTtmWaves) {
+      const int c = e / 32, k = e % 32;
+      T v = (T)0;
+      if (c < a.ell && k0 + k < a.n) v = (T)a.q[(k0 + k) + a.n * c];
+      slice[buf][c * kSlicePitch + k] = v;
+    }
+  };
+
+  const int nslices = (int)((a.n + 31) / 32);
+  stage(0, 0);
+  __syncthreads();
+  for (int s = 0; s < nslices; ++s) {
+    const int buf = s & 1;
+    const int64_t k0 = (int64_t)s * 32;
+    if (s + 1 < nslices) stage(buf ^ 1, k0 + 32);
+    if (active) {
+      const T* sl = slice[buf];
+      if constexpr (MODE0) {
+        typename Pol::Frag bf[NT];
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+          T v[8];
+#pragma unroll
+          for (int j = 0; j < 8; ++j) v[j] = sl[(16 * t + n) * kSlicePitch + tkmap<Tin, KVEC>(g, j)];
+          bf[t] = Pol::make(v);
+        }
+#pragma unroll
+        for (int m = 0; m < MT; ++m) {
+          const int64_t qi = q0 + 16 * m + n;
+          const bool qv = qi < a.Q;
+          const int64_t base = k0 + a.n * qi;
+          T v[8];
+          if constexpr (KVEC) {
+            if constexpr (sizeof(Tin) == 4) {
+#pragma unroll
+              for (int h = 0; h < 2; ++h) {
+                const int kk = 4 * g + 16 * h;
+                float4 x = make_float4(0.f, 0.f, 0.f, 0.f);
+                if (qv && k0 + kk < a.n) x = *reinterpret_cast<const float4*>(G + base + kk);
+                v[4 * h + 0] = (T)x.x;
+                v[4 * h + 1] = (T)x.y;
+                v[4 * h + 2] = (T)x.z;
+                v[4 * h + 3] = (T)x.w;
+              }
+            } else {
+#pragma unroll
+              for (int h = 0; h < 4; ++h) {
+                const int kk = 2 * g + 8 * h;
+                double2 x = make_double2(0.0, 0.0);
+                if (qv && k0 + kk < a.n) x = *reinterpret_cast<const double2*>(G + base + kk);
+                v[2 * h + 0] = (T)x.x;
+                v[2 * h + 1] = (T)x.y;
+              }
+            }
+          } else {
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+              const int kk = 8 * g + j;
+              Tin x = (Tin)0;
+              if (qv && k0 + kk < a.n) x = G[base + kk];
+              v[j] = (T)x;
+            }
+          }
+          const typename Pol::Frag af = Pol::make(v);
+#pragma unroll
+          for (int t = 0; t < NT; ++t) Pol::mma(acc[m][t], af, bf[t]);
+        }
+      } else {
+        typename Pol::Frag af[MT];
+#pragma unroll
+        for (int m = 0; m < MT; ++m) {
+          T v[8];
+#pragma unroll
+          for (int j = 0; j < 8; ++j) v[j] = sl[(16 * m + n) * kSlicePitch + 8 * g + j];
+          af[m] = Pol::make(v);
+        }
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+          const int64_t pi = p0 + 16 * t + n;
+          const bool pv = pi < a.P;
+          T v[8];
+#pragma unroll
+          for (int j = 0; j < 8; ++j) {
+            const int64_t ai = k0 + 8 * g + j;
+            Tin x = (Tin)0;
+            if (pv && ai < a.n) x = G[pi + a.P * (ai + a.n * qq)];
+            v[j] = (T)x;
+          }
+          const typename Pol::Frag bfr = Pol::make(v);
+#pragma unroll
+          for (int m = 0; m < MT; ++m) Pol::mma(acc[m][t], af[m], bfr);
+        }
+      }
+    }
+    __syncthreads();
+  }
+
+  if (!active) return;
+  Tout* out = reinterpret_cast<Tout*>(a.out);
+#pragma unroll
+  for (int m = 0; m < MT; ++m)
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        if constexpr (MODE0) {
+          const int64_t qi = q0 + 16 * m + Pol::out_row(g, r);
+          const int c = 16 * t + n;
+          if (qi < a.Q && c < a.ell) out[c + (int64_t)a.ell * qi] = (Tout)acc[m][t][r];
+        } else {
+          const int c = 16 * m + Pol::out_row(g, r);
+          const int64_t pi = p0 + 16 * t + n;
+          if (pi < a.P && c < a.ell) out[pi + a.P * (c + (int64_t)a.ell * qq)] = (Tout)acc[m][t][r];
+        }
+      }
+}
+
+template <typename Tin, int P, bool MODE0, bool KVEC, int MT, int NT>
+hipError_t ttm_go(const TtmArgs& a, hipStream_t st) {
+  const unsigned grid = (unsigned)((a.items + kTtmWaves - 1) / kTtmWaves);
+  hipLaunchKernelGGL((ttm_kernel<Tin, P, MODE0, KVEC, MT, NT>), dim3(grid), dim3(64 * kTtmWaves), 0,
+                     st, a);
+  return hipGetLastError();
+}
+
+template <typename Tin, int P>
+hipError_t ttm_dispatch(bool mode0, bool kvec, int tiles_c, const TtmArgs& a, hipStream_t st) {
+  if (mode0) {
+    if (kvec) {
+      switch (tiles_c) {
+        case 1: return ttm_go<Tin, P, true, true, 4, 1>(a, st);
+        case 2: return ttm_go<Tin, P, true, true, 4, 2>(a, st);
+        case 3: return ttm_go<Tin, P, true, true, 4, 3>(a, st);
+        default: return ttm_go<Tin, P, true, true, 4, 4>(a, st);
+      }
+    }
+    switch (tiles_c) {
+      case 1: return ttm_go<Tin, P, true, false, 4, 1>(a, st);
+      case 2: return ttm_go<Tin, P, true, false, 4, 2>(a, st);
+      case 3: return ttm_go<Tin, P, true, false, 4, 3>(a, st);
+      default: return ttm_go<Tin, P, true, false, 4, 4>(a, st);
+    }
+  }
+  switch (tiles_c) {
+    case 1: return ttm_go<Tin, P, false, false, 1, 2>(a, st);
+    case 2: return ttm_go<Tin, P, false, false, 2, 2>(a, st);
+    case 3: return ttm_go<Tin, P, false, false, 3, 2>(a, st);
+    default: return ttm_go<Tin, P, false, false, 4, 2>(a, st);
+  }
+}
+
+}  // namespace
+
+hipError_t launch_ttm(const TtmProblem& pb, void* /*qbuf*/, hipStream_t st) {
+  if (pb.ell < 1 || pb.ell > 64) return hipErrorInvalidValue;
+  TtmArgs a{};
+  a.g = pb.g;
+  a.out = pb.out;
+  a.q = pb.q64;
+  int64_t P = 1, Q = 1;
+  for (int k = 0; k < pb.mode; ++k) P *= pb.dims[k];
+  for (int k = pb.mode + 1; k < pb.d; ++k) Q *= pb.dims[k];
+  a.P = P;
+  a.n = pb.dims[pb.mode];
+  a.Q = Q;
+  a.ell = pb.ell;
+  const int tiles_c = (pb.ell + 15) / 16;
+  const bool mode0 = (P == 1);
+  const int vec = pb.g_is_double ? 2 : 4;
+  const bool kvec = mode0 && (a.n % vec == 0) && ((reinterpret_cast<uintptr_t>(pb.g) & 15) == 0);
+  if (mode0) {
+    a.items = (Q + 63) / 64;
+    a.p_groups = 1;
+  } else {
+    a.p_groups = (int)((P + 31) / 32);
+    a.items = Q * a.p_groups;
+  }
+  if (a.items == 0) return hipSuccess;
+  const bool wants_double_out = pb.prec == kFP64;
+  if (wants_double_out != (pb.out_is_double != 0)) return hipErrorInvalidValue;
+  if (pb.g_is_double) {
+    if (pb.prec != kFP64) return hipErrorInvalidValue;
+    return ttm_dispatch<double, kFP64>(mode0, kvec, tiles_c, a, st);
+  }
+  switch (pb.prec) {
+    case kFP64: return ttm_dispatch<float, kFP64>(mode0, kvec, tiles_c, a, st);
+    case kFP32: return ttm_dispatch<float, kFP32>(mode0, kvec, tiles_c, a, st);
+    case kBF16: return ttm_dispatch<float, kBF16>(mode0, kvec, tiles_c, a, st);
+    default: return ttm_dispatch<float, kBF16X3>(mode0, kvec, tiles_c, a, st);
+  }
+}
+
+size_t ttm_qbuf_bytes(int64_t, int) { return 0; }
+
+}  // namespace krp

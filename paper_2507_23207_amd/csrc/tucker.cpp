@@ -1,0 +1,438 @@
+// Drivers of krp_sketch, krp_hosvd (Algorithm 7) and krp_sthosvd
+// (Algorithm 8): validation, planning, workspace layout and the launch
+// sequence (captured into a HIP graph unless KRP_FLAG_NO_GRAPH).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/krp.h"
+#include "driver.h"
+#include "kernels.h"
+#include "truncate.h"
+
+namespace krp {
+
+namespace {
+
+constexpr int kSumScratch = 4096;
+constexpr int kMaxEll = 64;
+
+int validate_tensor(const void* X, int dtype, int d, const int64_t* dims, int prec) {
+  if (!X) return set_error(KRP_EINVAL, "X is NULL");
+  if (dtype != KRP_F64 && dtype != KRP_F32) return set_error(KRP_EINVAL, "unknown dtype %d", dtype);
+  if (d < 2 || d > kMaxDims) return set_error(KRP_EINVAL, "order d=%d outside 2..%d", d, kMaxDims);
+  if (!dims) return set_error(KRP_EINVAL, "dims is NULL");
+  double total = 1.0;
+  for (int k = 0; k < d; ++k) {
+    if (dims[k] < 1) return set_error(KRP_EINVAL, "dims[%d]=%lld must be >= 1", k, (long long)dims[k]);
+    total *= (double)dims[k];
+  }
+  if (total > 4.0e18) return set_error(KRP_EINVAL, "tensor too large");
+  if (prec < KRP_P_FP64 || prec > KRP_P_BF16X3) return set_error(KRP_EINVAL, "unknown precision %d", prec);
+  if (dtype == KRP_F64 && prec != KRP_P_FP64)
+    return set_error(KRP_EINVAL, "fp64 data requires KRP_P_FP64 arithmetic");
+  return KRP_OK;
+}
+
+struct TuckerSetup {
+  bool sthosvd = false;
+  int d = 0, dtype = 0, prec = 0;
+  bool out64 = false;  // intermediate cores in fp64
+  int64_t dims[kMaxDims]{};
+  int rank[kMaxDims]{}, ell[kMaxDims]{}, order[kMaxDims]{};
+  int n_sketch = 0;
+  SketchProblem spb[kMaxDims];
+  SketchPlan spl[kMaxDims];
+  int ttm_mode[kMaxDims]{};
+  int64_t ttm_in_dims[kMaxDims][kMaxDims]{};
+  int64_t ttm_out_elems[kMaxDims]{};
+  // workspace layout
+  size_t off_status = 0, off_sum = 0, off_norm = 0, off_y64 = 0, off_part = 0;
+  size_t off_q64[kMaxDims]{};
+  size_t off_core[2]{}, off_err[2]{}, off_trunc = 0;
+  size_t total = 0;
+  TruncPlan trunc;
+};
+
+int plan_tucker(bool sthosvd, int dtype, int d, const int64_t* dims, const int32_t* rank,
+                int32_t oversample, const krp_opts& o, TuckerSetup& s) {
+  s.sthosvd = sthosvd;
+  s.d = d;
+  s.dtype = dtype;
+  s.prec = o.prec;
+  s.out64 = (o.prec == KRP_P_FP64);
+  if (!rank) return set_error(KRP_EINVAL, "rank is NULL");
+  if (oversample < 0) return set_error(KRP_EINVAL, "oversample must be >= 0");
+  for (int k = 0; k < d; ++k) {
+    s.dims[k] = dims[k];
+    if (rank[k] < 1) return set_error(KRP_EINVAL, "rank[%d]=%d must be >= 1", k, rank[k]);
+    const int64_t l = (int64_t)rank[k] + oversample;
+    if (l > dims[k])
+      return set_error(KRP_EINVAL, "ell[%d]=%lld exceeds the mode size %lld", k, (long long)l,
+                       (long long)dims[k]);
+    if (l > kMaxEll) return set_error(KRP_EINVAL, "ell[%d]=%lld exceeds the supported 64", k, (long long)l);
+    s.rank[k] = rank[k];
+    s.ell[k] = (int)l;
+  }
+  if (o.order) {
+    if (!sthosvd) return set_error(KRP_EINVAL, "a mode order applies to krp_sthosvd only");
+    bool seen[kMaxDims] = {false};
+    for (int k = 0; k < d; ++k) {
+      const int m = o.order[k];
+      if (m < 0 || m >= d || seen[m]) return set_error(KRP_EINVAL, "order is not a permutation of 0..d-1");
+      seen[m] = true;
+      s.order[k] = m;
+    }
+  } else {
+    for (int k = 0; k < d; ++k) s.order[k] = k;
+  }
+  if (o.truncate != 0 && o.truncate != 1) return set_error(KRP_EINVAL, "truncate must be 0 or 1");
+
+  const size_t cs = s.out64 ? 8 : 4;
+  size_t part_max = 0, y_max = 0, core_max = 0, err_max = 0;
+  int64_t cur[kMaxDims];
+  for (int k = 0; k < d; ++k) cur[k] = dims[k];
+  SketchTile tile;
+  for (int step = 0; step < d; ++step) {
+    const int m = sthosvd ? s.order[step] : step;
+    SketchProblem& pb = s.spb[step];
+    pb.x_is_double = (step == 0 || !sthosvd) ? (dtype == KRP_F64) : s.out64;
+    pb.d = d;
+    for (int k = 0; k < d; ++k) pb.dims[k] = sthosvd ? cur[k] : dims[k];
+    pb.mode = m;
+    pb.ell = s.ell[m];
+    pb.prec = o.prec;
+    pb.seed = o.seed;
+    pb.draw = o.draw;
+    pb.sketch_id = (uint32_t)m;
+    s.spl[step] = plan_sketch(pb, tile);
+    part_max = std::max(part_max, s.spl[step].partial_bytes);
+    y_max = std::max(y_max, (size_t)(pb.dims[m] * s.ell[m]));
+    if (sthosvd) {
+      s.ttm_mode[step] = m;
+      for (int k = 0; k < d; ++k) s.ttm_in_dims[step][k] = cur[k];
+      cur[m] = s.ell[m];
+      int64_t e = 1;
+      for (int k = 0; k < d; ++k) e *= cur[k];
+      s.ttm_out_elems[step] = e;
+      core_max = std::max(core_max, (size_t)e);
+    }
+  }
+  s.n_sketch = d;
+  // TTM chain of Algorithm 7 (natural order) and of the error check.
+  for (int k = 0; k < d; ++k) cur[k] = dims[k];
+  for (int step = 0; step < d; ++step) {
+    if (!sthosvd) {
+      s.ttm_mode[step] = step;
+      for (int k = 0; k < d; ++k) s.ttm_in_dims[step][k] = cur[k];
+    }
+    cur[step] = s.ell[step];
+    int64_t e = 1;
+    for (int k = 0; k < d; ++k) e *= cur[k];
+    if (!sthosvd) {
+      s.ttm_out_elems[step] = e;
+      core_max = std::max(core_max, (size_t)e);
+    }
+    err_max = std::max(err_max, (size_t)e);
+  }
+  size_t off = 0;
+  s.off_status = off; off = align_up(off + 64);
+  s.off_norm = off; off = align_up(off + 4 * sizeof(double));
+  s.off_sum = off; off = align_up(off + kSumScratch * sizeof(double));
+  s.off_y64 = off; off = align_up(off + y_max * sizeof(double));
+  for (int k = 0; k < d; ++k) {
+    s.off_q64[k] = off;
+    off = align_up(off + (size_t)dims[k] * s.ell[k] * sizeof(double));
+  }
+  s.off_part = off; off = align_up(off + part_max);
+  s.off_core[0] = off; off = align_up(off + core_max * cs);
+  s.off_core[1] = off; off = align_up(off + core_max * cs);
+  s.off_err[0] = off; off = align_up(off + err_max * sizeof(double));
+  s.off_err[1] = off; off = align_up(off + err_max * sizeof(double));
+  // truncation of the ell-sized core (fp64)
+  s.trunc = plan_truncate(d, s.ell, s.rank, dims, s.order);
+  s.off_trunc = off; off = align_up(off + s.trunc.ws_bytes);
+  s.total = off;
+  return KRP_OK;
+}
+
+std::string tucker_key(const TuckerSetup& s, const krp_opts& o, const void* X, const void* core,
+                       void* const* Q, const void* ws, const int* status, bool want_err) {
+  std::string k = s.sthosvd ? "sthosvd" : "hosvd";
+  k += "|dt=" + std::to_string(s.dtype) + "|p=" + std::to_string(s.prec);
+  for (int i = 0; i < s.d; ++i)
+    k += "|" + std::to_string(s.dims[i]) + "," + std::to_string(s.rank[i]) + "," +
+         std::to_string(s.ell[i]) + "," + std::to_string(s.order[i]) + "," + ptr_key(Q[i]);
+  k += "|seed=" + std::to_string(o.seed) + "|draw=" + std::to_string(o.draw) +
+       "|tr=" + std::to_string(o.truncate) + "|err=" + std::to_string(want_err ? 1 : 0) +
+       "|X=" + ptr_key(X) + "|core=" + ptr_key(core) + "|ws=" + ptr_key(ws) + "|" +
+       "|st=" + ptr_key(status);
+  return k;
+}
+
+int check(hipError_t e, const char* what) { return e == hipSuccess ? KRP_OK : hip_fail(e, what); }
+
+#define KRP_TRY(expr)            \
+  do {                           \
+    const int _rc = (expr);      \
+    if (_rc != KRP_OK) return _rc; \
+  } while (0)
+
+int enqueue_tucker(const TuckerSetup& s, const krp_opts& o, const void* X, void* core,
+                   void* const* Q, char* ws, int* status, bool want_err, hipStream_t st) {
+  const int d = s.d;
+  const bool x64 = s.dtype == KRP_F64;
+  const bool trunc = o.truncate == 1;
+  if (!o.status_dev) KRP_TRY(check(launch_fill_int(status, 0, 1, st), "fill"));
+  double* y64 = reinterpret_cast<double*>(ws + s.off_y64);
+  void* part = ws + s.off_part;
+  void* cores[2] = {ws + s.off_core[0], ws + s.off_core[1]};
+  const void* cur = X;
+  bool cur64 = x64;
+  for (int step = 0; step < d; ++step) {
+    const int m = s.spb[step].mode;
+    SketchProblem pb = s.spb[step];
+    pb.x = s.sthosvd ? cur : X;
+    pb.x_is_double = s.sthosvd ? (cur64 ? 1 : 0) : (x64 ? 1 : 0);
+    KRP_TRY(check(launch_sketch(pb, s.spl[step], part, y64, nullptr, 0, st), "sketch"));
+    double* q64 = reinterpret_cast<double*>(ws + s.off_q64[m]);
+    KRP_TRY(check(launch_cholqr(1, pb.dims[m], s.ell[m], y64, q64, trunc ? nullptr : Q[m], x64 ? 1 : 0,
+                                nullptr, nullptr, status, st),
+                  "cholqr"));
+    if (s.sthosvd) {
+      TtmProblem tp;
+      tp.g = cur;
+      tp.g_is_double = cur64 ? 1 : 0;
+      tp.d = d;
+      for (int k = 0; k < d; ++k) tp.dims[k] = s.ttm_in_dims[step][k];
+      tp.mode = m;
+      tp.ell = s.ell[m];
+      tp.prec = s.prec;
+      tp.q64 = q64;
+      tp.out = cores[step & 1];
+      tp.out_is_double = s.out64 ? 1 : 0;
+      KRP_TRY(check(launch_ttm(tp, nullptr, st), "ttm"));
+      cur = tp.out;
+      cur64 = s.out64;
+    }
+  }
+  if (!s.sthosvd) {
+    cur = X;
+    cur64 = x64;
+    for (int step = 0; step < d; ++step) {
+      TtmProblem tp;
+      tp.g = cur;
+      tp.g_is_double = cur64 ? 1 : 0;
+      tp.d = d;
+      for (int k = 0; k < d; ++k) tp.dims[k] = s.ttm_in_dims[step][k];
+      tp.mode = step;
+      tp.ell = s.ell[step];
+      tp.prec = s.prec;
+      tp.q64 = reinterpret_cast<double*>(ws + s.off_q64[step]);
+      tp.out = cores[step & 1];
+      tp.out_is_double = s.out64 ? 1 : 0;
+      KRP_TRY(check(launch_ttm(tp, nullptr, st), "ttm"));
+      cur = tp.out;
+      cur64 = s.out64;
+    }
+  }
+  // `cur` holds the ell-sized core in the compute type.
+  if (trunc) {
+    double* qs[kMaxDims];
+    for (int k = 0; k < d; ++k) qs[k] = reinterpret_cast<double*>(ws + s.off_q64[k]);
+    KRP_TRY(check(launch_truncate(s.trunc, cur, cur64 ? 1 : 0, qs, core, Q, x64 ? 1 : 0,
+                                  ws + s.off_trunc, st),
+                  "truncate"));
+  } else {
+    int64_t elems = 1;
+    for (int k = 0; k < d; ++k) elems *= s.ell[k];
+    KRP_TRY(check(launch_cast(cur, cur64 ? 1 : 0, core, x64 ? 1 : 0, elems, st), "cast core"));
+  }
+  if (want_err) {
+    // ||X||^2 and ||X x_1 Q_1^T ... x_d Q_d^T||^2 in fp64 with the fp64 factors
+    // (the projection identity for orthonormal Q_i).
+    double* norms = reinterpret_cast<double*>(ws + s.off_norm);
+    double* scratch = reinterpret_cast<double*>(ws + s.off_sum);
+    int64_t nx = 1;
+    for (int k = 0; k < d; ++k) nx *= s.dims[k];
+    KRP_TRY(check(launch_sumsq(X, x64 ? 1 : 0, nx, norms + 0, scratch, kSumScratch, st), "sumsq"));
+    const void* e_cur = X;
+    bool e64 = x64;
+    int64_t edims[kMaxDims];
+    for (int k = 0; k < d; ++k) edims[k] = s.dims[k];
+    int64_t elems = 0;
+    for (int step = 0; step < d; ++step) {
+      const int r = trunc ? s.rank[step] : s.ell[step];
+      TtmProblem tp;
+      tp.g = e_cur;
+      tp.g_is_double = e64 ? 1 : 0;
+      tp.d = d;
+      for (int k = 0; k < d; ++k) tp.dims[k] = edims[k];
+      tp.mode = step;
+      tp.ell = r;
+      tp.prec = KRP_P_FP64;
+      tp.q64 = trunc ? truncated_q64(s.trunc, ws + s.off_trunc, step)
+                     : reinterpret_cast<double*>(ws + s.off_q64[step]);
+      tp.out = ws + s.off_err[step & 1];
+      tp.out_is_double = 1;
+      KRP_TRY(check(launch_ttm(tp, nullptr, st), "ttm(err)"));
+      e_cur = tp.out;
+      e64 = true;
+      edims[step] = r;
+    }
+    elems = 1;
+    for (int k = 0; k < d; ++k) elems *= edims[k];
+    KRP_TRY(check(launch_sumsq(e_cur, 1, elems, norms + 1, scratch, kSumScratch, st), "sumsq"));
+  }
+  return KRP_OK;
+}
+
+int tucker_entry(bool sthosvd, const void* X, int dtype, int d, const int64_t* dims,
+                 const int32_t* rank, int32_t oversample, const krp_opts* opts, void* core,
+                 void* const* Q, int64_t* core_dims, void* stream) {
+  krp_opts o;
+  if (opts)
+    o = *opts;
+  else
+    krp_opts_default(&o);
+  KRP_TRY(validate_tensor(X, dtype, d, dims, o.prec));
+  if (!core) return set_error(KRP_EINVAL, "core is NULL");
+  if (!Q) return set_error(KRP_EINVAL, "Q is NULL");
+  for (int k = 0; k < d; ++k)
+    if (!Q[k]) return set_error(KRP_EINVAL, "Q[%d] is NULL", k);
+  TuckerSetup s;
+  KRP_TRY(plan_tucker(sthosvd, dtype, d, dims, rank, oversample, o, s));
+  if (core_dims)
+    for (int k = 0; k < d; ++k) core_dims[k] = o.truncate ? s.rank[k] : s.ell[k];
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  char* ws = nullptr;
+  KRP_TRY(acquire_workspace(&o, s.total, st, &ws));
+  int* status = o.status_dev ? o.status_dev : reinterpret_cast<int*>(ws + s.off_status);
+  const bool want_err = o.rel_err != nullptr;
+  const std::string key = tucker_key(s, o, X, core, Q, ws, status, want_err);
+  KRP_TRY(run_maybe_graph(key, !(o.flags & KRP_FLAG_NO_GRAPH), st, [&](hipStream_t cs) {
+    return enqueue_tucker(s, o, X, core, Q, ws, status, want_err, cs);
+  }));
+  int rc = KRP_OK;
+  if (!o.status_dev) rc = finish_status(status, st);
+  if (want_err) {
+    double nrm[2] = {0.0, 0.0};
+    hipError_t e = hipMemcpyAsync(nrm, ws + s.off_norm, 2 * sizeof(double), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return hip_fail(e, "read norms");
+    *o.rel_err = nrm[0] > 0 ? std::sqrt(std::max(0.0, nrm[0] - nrm[1]) / nrm[0]) : 0.0;
+  }
+  return rc;
+}
+
+}  // namespace
+
+}  // namespace krp
+
+using namespace krp;
+
+extern "C" {
+
+int krp_sketch(const void* X, int dtype, int d, const int64_t* dims, int nmodes, const int32_t* modes,
+               const int32_t* ell, const krp_opts* opts, void* const* Y, void* stream) {
+  krp_opts o;
+  if (opts)
+    o = *opts;
+  else
+    krp_opts_default(&o);
+  KRP_TRY(validate_tensor(X, dtype, d, dims, o.prec));
+  if (nmodes < 1 || nmodes > d) return set_error(KRP_EINVAL, "nmodes=%d outside 1..d", nmodes);
+  if (!modes || !ell || !Y) return set_error(KRP_EINVAL, "modes, ell and Y must not be NULL");
+  bool seen[kMaxDims] = {false};
+  SketchProblem pbs[kMaxDims];
+  SketchPlan pls[kMaxDims];
+  size_t part = 0;
+  for (int j = 0; j < nmodes; ++j) {
+    const int m = modes[j];
+    if (m < 0 || m >= d || seen[m]) return set_error(KRP_EINVAL, "modes must be distinct values in 0..d-1");
+    seen[m] = true;
+    if (ell[j] < 1 || ell[j] > kMaxEll) return set_error(KRP_EINVAL, "ell[%d]=%d outside 1..64", j, ell[j]);
+    if (!Y[j]) return set_error(KRP_EINVAL, "Y[%d] is NULL", j);
+    SketchProblem& pb = pbs[j];
+    pb.x = X;
+    pb.x_is_double = dtype == KRP_F64;
+    pb.d = d;
+    for (int k = 0; k < d; ++k) pb.dims[k] = dims[k];
+    pb.mode = m;
+    pb.ell = ell[j];
+    pb.prec = o.prec;
+    pb.seed = o.seed;
+    pb.draw = o.draw;
+    pb.sketch_id = (uint32_t)m;
+    pls[j] = plan_sketch(pb, SketchTile{});
+    part = std::max(part, pls[j].partial_bytes);
+  }
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  char* ws = nullptr;
+  KRP_TRY(acquire_workspace(&o, align_up(part), st, &ws));
+  std::string key = "sketch|dt=" + std::to_string(dtype) + "|p=" + std::to_string(o.prec) +
+                    "|seed=" + std::to_string(o.seed) + "|draw=" + std::to_string(o.draw) +
+                    "|X=" + ptr_key(X) + "|ws=" + ptr_key(ws) + "|";
+  for (int k = 0; k < d; ++k) key += std::to_string(dims[k]) + ",";
+  for (int j = 0; j < nmodes; ++j)
+    key += "|" + std::to_string(modes[j]) + "," + std::to_string(ell[j]) + "," + ptr_key(Y[j]);
+  return run_maybe_graph(key, !(o.flags & KRP_FLAG_NO_GRAPH), st, [&](hipStream_t cs) -> int {
+    for (int j = 0; j < nmodes; ++j) {
+      KRP_TRY(check(launch_sketch(pbs[j], pls[j], ws, nullptr, Y[j], dtype == KRP_F64, cs), "sketch"));
+    }
+    return KRP_OK;
+  });
+}
+
+int krp_hosvd(const void* X, int dtype, int d, const int64_t* dims, const int32_t* rank,
+              int32_t oversample, const krp_opts* opts, void* core, void* const* Q, int64_t* core_dims,
+              void* stream) {
+  return tucker_entry(false, X, dtype, d, dims, rank, oversample, opts, core, Q, core_dims, stream);
+}
+
+int krp_sthosvd(const void* X, int dtype, int d, const int64_t* dims, const int32_t* rank,
+                int32_t oversample, const krp_opts* opts, void* core, void* const* Q, int64_t* core_dims,
+                void* stream) {
+  return tucker_entry(true, X, dtype, d, dims, rank, oversample, opts, core, Q, core_dims, stream);
+}
+
+int krp_workspace_size(int which, int dtype, int d, const int64_t* dims, const int32_t* rank,
+                       int32_t oversample, int prec, size_t* bytes) {
+  if (!bytes) return set_error(KRP_EINVAL, "bytes is NULL");
+  if (dtype != KRP_F64 && dtype != KRP_F32) return set_error(KRP_EINVAL, "unknown dtype %d", dtype);
+  if (d < 2 || d > kMaxDims || !dims || !rank) return set_error(KRP_EINVAL, "bad shape arguments");
+  if (prec < 0 || prec > 3 || (dtype == KRP_F64 && prec != KRP_P_FP64))
+    return set_error(KRP_EINVAL, "bad precision");
+  for (int k = 0; k < d; ++k)
+    if (dims[k] < 1) return set_error(KRP_EINVAL, "dims[%d] must be >= 1", k);
+  krp_opts o;
+  krp_opts_default(&o);
+  o.prec = prec;
+  if (which == 0) {
+    size_t part = 0;
+    for (int m = 0; m < d; ++m) {
+      if (rank[m] < 1 || rank[m] > kMaxEll) return set_error(KRP_EINVAL, "ell[%d] outside 1..64", m);
+      SketchProblem pb;
+      pb.x_is_double = dtype == KRP_F64;
+      pb.d = d;
+      for (int k = 0; k < d; ++k) pb.dims[k] = dims[k];
+      pb.mode = m;
+      pb.ell = rank[m];
+      pb.prec = prec;
+      part = std::max(part, plan_sketch(pb, SketchTile{}).partial_bytes);
+    }
+    *bytes = align_up(part);
+    return KRP_OK;
+  }
+  if (which != 1 && which != 2) return set_error(KRP_EINVAL, "which must be 0, 1 or 2");
+  TuckerSetup s;
+  KRP_TRY(plan_tucker(which == 2, dtype, d, dims, rank, oversample, o, s));
+  *bytes = s.total;
+  return KRP_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,127 @@
+"""C-ABI contract checks that need no GPU: symbols, defaults, argument errors."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2507_23207_amd import _capi
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+FAKE = ctypes.c_void_p(0x10000)  # never dereferenced: every call below fails validation first
+
+
+@pytest.fixture(scope="module")
+def L():
+    return _capi.lib()
+
+
+def _declared():
+    text = open(os.path.join(ROOT, "include", "krp.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(krp_[a-z_]+)\s*\(", text)))
+
+
+def test_header_and_binding_agree():
+    assert sorted(_capi.EXPORTED) == _declared()
+
+
+def test_library_exports_every_declared_symbol(L):
+    for name in _declared():
+        assert hasattr(L, name), name
+
+
+def test_opts_default(L):
+    o = _capi.KrpOpts()
+    L.krp_opts_default(ctypes.byref(o))
+    assert o.seed == 2507 and o.draw == 0 and o.prec == _capi.KRP_P_FP32
+    assert o.truncate == 0 and o.flags == 0 and not o.order and not o.workspace
+    assert ctypes.sizeof(_capi.KrpOpts) == 64
+
+
+def test_status_strings(L):
+    for code in range(7):
+        assert L.krp_status_string(code).decode().startswith("KRP_")
+    assert "libkrp" in L.krp_version().decode()
+
+
+def _sketch(L, X=FAKE, dtype=1, dims=(8, 8, 8), modes=(0,), ell=(4,), Y=(FAKE,), prec=1, d=None):
+    o = _capi.KrpOpts()
+    L.krp_opts_default(ctypes.byref(o))
+    o.prec = prec
+    d = len(dims) if d is None else d
+    return L.krp_sketch(X, dtype, d, _capi.i64_array(dims), len(modes), _capi.i32_array(modes),
+                        _capi.i32_array(ell), ctypes.byref(o), _capi.ptr_array([y.value for y in Y]), None)
+
+
+@pytest.mark.parametrize("kw", [
+    dict(X=ctypes.c_void_p(0)),
+    dict(dtype=7),
+    dict(dims=(8,)),
+    dict(dims=(8,) * 9),
+    dict(dims=(8, 0, 8)),
+    dict(prec=9),
+    dict(dtype=0, prec=1),          # fp64 data needs fp64 arithmetic
+    dict(modes=(3,)),
+    dict(modes=(0, 0), ell=(4, 4), Y=(FAKE, FAKE)),
+    dict(ell=(0,)),
+    dict(ell=(65,)),
+    dict(Y=(ctypes.c_void_p(0),)),
+])
+def test_sketch_rejects_before_gpu(L, kw):
+    assert _sketch(L, **kw) == _capi.KRP_EINVAL
+    assert L.krp_last_error().decode() != ""
+
+
+def _tucker(L, fn="krp_hosvd", dims=(8, 8, 8), rank=(2, 2, 2), p=2, order=None, truncate=0, q_null=False,
+            core=FAKE):
+    o = _capi.KrpOpts()
+    L.krp_opts_default(ctypes.byref(o))
+    o.truncate = truncate
+    keep = None
+    if order is not None:
+        keep = _capi.i32_array(order)
+        o.order = ctypes.cast(keep, ctypes.POINTER(ctypes.c_int32))
+    qs = [0 if q_null else FAKE.value] * len(dims)
+    return getattr(L, fn)(FAKE, 1, len(dims), _capi.i64_array(dims), _capi.i32_array(rank), p,
+                          ctypes.byref(o), core, _capi.ptr_array(qs), None, None)
+
+
+@pytest.mark.parametrize("fn", ["krp_hosvd", "krp_sthosvd"])
+@pytest.mark.parametrize("kw", [
+    dict(rank=(0, 2, 2)),
+    dict(rank=(7, 2, 2)),              # ell = 9 > 8
+    dict(dims=(100, 100, 100), rank=(63, 2, 2)),  # ell = 65 > 64
+    dict(p=-1),
+    dict(q_null=True),
+    dict(core=ctypes.c_void_p(0)),
+    dict(truncate=2),
+])
+def test_tucker_rejects_before_gpu(L, fn, kw):
+    assert _tucker(L, fn=fn, **kw) == _capi.KRP_EINVAL
+
+
+def test_order_validation(L):
+    assert _tucker(L, fn="krp_sthosvd", order=(0, 0, 1)) == _capi.KRP_EINVAL
+    assert _tucker(L, fn="krp_sthosvd", order=(0, 1, 5)) == _capi.KRP_EINVAL
+    assert _tucker(L, fn="krp_hosvd", order=(2, 1, 0)) == _capi.KRP_EINVAL
+
+
+def test_gaussian_rejects(L):
+    assert L.krp_gaussian(1, 0, 0, 0, 0, -1, 3, 0, FAKE, None) == _capi.KRP_EINVAL
+    assert L.krp_gaussian(1, 0, 0, 0, 0, 3, 3, 7, FAKE, None) == _capi.KRP_EINVAL
+    assert L.krp_gaussian(1, 0, 1 << 16, 0, 0, 3, 3, 0, FAKE, None) == _capi.KRP_EINVAL
+    assert L.krp_gaussian(1, 0, 0, 0, 0, 3, 3, 0, ctypes.c_void_p(0), None) == _capi.KRP_EINVAL
+
+
+def test_workspace_size_queries(L):
+    nb = ctypes.c_size_t(0)
+    dims = _capi.i64_array((64, 64, 64))
+    rank = _capi.i32_array((8, 8, 8))
+    for which in (1, 2):
+        assert L.krp_workspace_size(which, 0, 3, dims, rank, 5, 0, ctypes.byref(nb)) == _capi.KRP_OK
+        assert nb.value > 64 * 13 * 8 * 3
+    assert L.krp_workspace_size(0, 1, 3, dims, _capi.i32_array((13, 13, 13)), 0, 3, ctypes.byref(nb)) == 0
+    assert nb.value > 0
+    assert L.krp_workspace_size(5, 1, 3, dims, rank, 5, 1, ctypes.byref(nb)) == _capi.KRP_EINVAL
+    assert L.krp_workspace_size(1, 0, 3, dims, rank, 5, 1, ctypes.byref(nb)) == _capi.KRP_EINVAL
