@@ -63,53 +63,65 @@ def sthosvd_bytes(dims, ells, elem):
 
 
 def time_calls(fn, steps, warmup, stream):
+    """Wall-clock ms per call (synchronised on both sides, the step contract)."""
     import torch
     for _ in range(warmup):
         fn()
     torch.cuda.synchronize()
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
     t0 = time.perf_counter()
-    for a, b in ev:
-        a.record(stream)
+    for _ in range(steps):
         fn()
-        b.record(stream)
     torch.cuda.synchronize()
-    wall = (time.perf_counter() - t0) / steps
-    ms = [a.elapsed_time(b) for a, b in ev]
-    return sum(ms) / len(ms), wall * 1e3
+    return (time.perf_counter() - t0) / steps * 1e3
 
 
-def cpu_baseline(x_np, ranks, p, sample_modes=1):
-    """The fp64 oracle (explicit KRPs and unfoldings) on the host cores.
+def gpu_ms(fn, reps, stream):
+    """GPU time per call from HIP events on `stream`.
 
-    Sample: the first `sample_modes` mode steps of Algorithm 8 (sketch, QR,
-    TTM) on the full tensor; the rate is algorithmic bytes of those steps per
-    second, in the same unit as the GPU value."""
+    A spin kernel keeps the GPU busy while the calls are enqueued, so the
+    interval between the two events holds only the calls' own kernels."""
+    import torch
+    fn()
+    torch.cuda.synchronize()
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    torch.cuda._sleep(int(2.0e7))
+    a.record(stream)
+    for _ in range(reps):
+        fn()
+    b.record(stream)
+    torch.cuda.synchronize()
+    return a.elapsed_time(b) / reps
+
+
+def cpu_baseline(x_np, ranks, p, min_seconds=10.0):
+    """The fp64 oracle (explicit KRPs, unfoldings, LAPACK) on the host cores.
+
+    Sample: complete steps (Algorithm 8 on the full tensor, then the core
+    truncation) repeated until `min_seconds` have elapsed; the rate is the
+    step's algorithmic bytes per second, in the unit of the GPU value."""
     import numpy as np
-    from oracle import rng as orng
     from oracle import tucker as ot
-    from oracle.linalg import qr_pos
-    from oracle.tensor import mttkrp, ttm
 
-    g = np.asarray(x_np, dtype=np.float64)
-    dims = list(g.shape)
+    x = np.asarray(x_np, dtype=np.float64)
+    dims = list(x.shape)
     ells = [r + p for r in ranks]
-    nbytes = 0
+    step_bytes = sthosvd_bytes(dims, ells, 4)
+    reps = 0
     t0 = time.perf_counter()
-    for i in range(sample_modes):
-        f = ot.sketch_factors(2507, 0, i, g.shape, ells[i], i)
-        y = mttkrp(g, f, i)
-        q = qr_pos(y)[0]
-        size = g.size
-        g = ttm(g, q.T, i)
-        nbytes += size * 4 + dims[i] * ells[i] * 4 + size * 4 + g.size * 4
-    dt = time.perf_counter() - t0
+    while True:
+        g, qs = ot.rsthosvd_krp(x, ranks, p)
+        ot.truncate(g, qs, ranks)
+        reps += 1
+        dt = time.perf_counter() - t0
+        if dt >= min_seconds:
+            break
     threads = os.environ.get("OPENBLAS_NUM_THREADS") or os.environ.get("OMP_NUM_THREADS")
     cores = int(threads) if threads else (os.cpu_count() or 1)
-    return dict(value=nbytes / dt / 1e9, unit="GB/s", cores=cores, kind="oracle",
-                sample=f"Algorithm 8 mode-{sample_modes} prefix (explicit-KRP sketch, LAPACK QR, "
-                       f"unfolding TTM) of the full {'x'.join(map(str, dims))} tensor in fp64: "
-                       f"{nbytes / 1e9:.2f} GB algorithmic in {dt:.2f} s")
+    return dict(value=step_bytes * reps / dt / 1e9, unit="GB/s", cores=cores, kind="oracle",
+                sample=f"{reps} full step(s) (Algorithm 8 with explicit KRPs and unfoldings, then the "
+                       f"core truncation) on the {'x'.join(map(str, dims))} tensor in fp64, "
+                       f"{dt:.1f} s", s_per_step=dt / reps)
 
 
 def main():
@@ -139,7 +151,8 @@ def main():
     def step():
         return krp.sthosvd(x, ranks, p, prec=args.prec, truncate=True)
 
-    step_ms, step_wall_ms = time_calls(step, args.steps, args.warmup, stream)
+    step_ms = time_calls(step, args.steps, args.warmup, stream)
+    step_gpu_ms = gpu_ms(step, args.steps, stream)
     core, qs, err_mixed = krp.sthosvd(x, ranks, p, prec=args.prec, truncate=True, rel_err=True)
     step_bytes = sthosvd_bytes(dims, ells, 4)
 
@@ -147,7 +160,7 @@ def main():
     sketch = {}
     for m in range(len(dims)):
         fn = lambda m=m: krp.sketch(x, [m], [ells[m]], prec=args.prec)
-        ms, _ = time_calls(fn, max(5, args.steps), 2, stream)
+        ms = gpu_ms(fn, max(10, args.steps), stream)
         b = x.numel() * 4 + dims[m] * ells[m] * 4
         sketch[m] = dict(ms=ms, gbps=b / ms / 1e6, bytes=b)
 
@@ -157,9 +170,11 @@ def main():
         x64 = x.to(torch.float64)  # converted once, outside the timed region
         def step64():
             return krp.sthosvd(x64, ranks, p, prec="fp64", truncate=True)
-        ms64, _ = time_calls(step64, max(3, args.steps // 2), 2, stream)
+        ms64 = time_calls(step64, max(3, args.steps // 2), 2, stream)
+        gms64 = gpu_ms(step64, max(3, args.steps // 2), stream)
         _, _, err64 = krp.sthosvd(x64, ranks, p, prec="fp64", truncate=True, rel_err=True)
-        fp64 = dict(ms=ms64, tucker_rel_err=err64, speedup_mixed=ms64 / step_ms,
+        fp64 = dict(ms=ms64, gpu_ms=gms64, tucker_rel_err=err64, speedup_mixed=ms64 / step_ms,
+                    speedup_mixed_gpu=gms64 / step_gpu_ms,
                     err_ratio=err_mixed / err64)
         del x64
 
@@ -167,7 +182,7 @@ def main():
     if not args.no_cpu_baseline:
         x_np = x.permute(*reversed(range(len(dims)))).contiguous().cpu().numpy()
         x_np = np.ascontiguousarray(x_np).transpose(*reversed(range(len(dims))))
-        cpu = cpu_baseline(x_np, ranks, p, sample_modes=1)
+        cpu = cpu_baseline(x_np, ranks, p)
 
     dom = sketch[0]
     out = {
@@ -195,7 +210,7 @@ def main():
         "cpu_baseline": cpu,
         "sketch_gbps_by_mode": [sketch[m]["gbps"] for m in range(len(dims))],
         "sketch_ms_by_mode": [sketch[m]["ms"] for m in range(len(dims))],
-        "step_wall_ms": step_wall_ms,
+        "step_gpu_ms": step_gpu_ms,
         "tucker_rel_err_mixed": err_mixed,
         "fp64_form": fp64,
     }

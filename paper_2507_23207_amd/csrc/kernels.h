@@ -14,7 +14,7 @@ struct SketchTile {
   int wm = 0;         // waves along the rows (0: derived from the row count)
   int wo = 0;         // waves splitting the outer iterations (0: derived)
   int64_t o_per_wg = 0;  // outer iterations per workgroup (0: derived)
-  int target_wgs = 512;  // workgroups aimed for when deriving o_per_wg
+  int target_wgs = 256;  // workgroups aimed for when deriving o_per_wg
 };
 
 // Problem description of a single-mode MTTKRP sketch

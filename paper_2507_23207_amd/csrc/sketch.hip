@@ -56,7 +56,7 @@ __global__ __launch_bounds__(512) void sketch_kernel(SketchArgs a) {
   T* tab = reinterpret_cast<T*>(smem_raw);
 
   const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int w_m = wave % a.wm;
   const int w_o = wave / a.wm;
   const int kg = blockIdx.x;
@@ -129,12 +129,6 @@ __global__ __launch_bounds__(512) void sketch_kernel(SketchArgs a) {
   }
   __syncthreads();
 
-  T wf[NT][8];
-#pragma unroll
-  for (int t = 0; t < NT; ++t)
-#pragma unroll
-    for (int j = 0; j < 8; ++j) wf[t][j] = tab[kmap<Tin, KVEC>(g, j) * CP + 16 * t + n];
-
   typename Pol::Acc acc[MT][NT];
 #pragma unroll
   for (int m = 0; m < MT; ++m)
@@ -142,31 +136,52 @@ __global__ __launch_bounds__(512) void sketch_kernel(SketchArgs a) {
     for (int t = 0; t < NT; ++t) acc[m][t] = Pol::zero();
 
   const Tin* X = reinterpret_cast<const Tin*>(a.x);
-  for (int64_t o = o_begin + w_o; o < o_end; o += a.wo) {
-    int64_t off = 0;
-    T w[NT];
-#pragma unroll
-    for (int t = 0; t < NT; ++t) w[t] = (T)1;
+  // Outer index o as an odometer (digits, element offset, table rows): the
+  // wave starts at o_begin + w_o and advances by wo.  All uniform (SGPRs).
+  struct Odo {
+    int64_t o, off;
+    int64_t dig[kMaxDims];
+  };
+  auto odo_init = [&](int64_t o) {
+    Odo z;
+    z.o = o;
+    z.off = 0;
     int64_t rem = o;
 #pragma unroll
     for (int k = 0; k < kMaxDims; ++k) {
+      z.dig[k] = 0;
       if (k < a.n_out) {
-        const int64_t dk = rem % a.o_size[k];
+        z.dig[k] = rem % a.o_size[k];
         rem /= a.o_size[k];
-        off += dk * a.o_stride[k];
-        const int rr = toff[k] + (int)((dk - lo[k] + a.o_size[k]) % a.o_size[k]);
-#pragma unroll
-        for (int t = 0; t < NT; ++t) w[t] = w[t] * tab[rr * CP + 16 * t + n];
+        z.off += z.dig[k] * a.o_stride[k];
       }
     }
-
-    // A fragments (all M tiles first, so their loads are in flight together).
-    T av[MT][8];
+    return z;
+  };
+  auto odo_step = [&](Odo& z, int by) {
+    z.o += by;
+    int64_t carry = by;
+#pragma unroll
+    for (int k = 0; k < kMaxDims; ++k) {
+      if (k < a.n_out && carry != 0) {
+        int64_t dnew = z.dig[k] + carry;
+        carry = 0;
+        while (dnew >= a.o_size[k]) {
+          dnew -= a.o_size[k];
+          ++carry;
+        }
+        z.off += (dnew - z.dig[k]) * a.o_stride[k];
+        z.dig[k] = dnew;
+      }
+    }
+  };
+  // A fragments of outer step z (raw input values, converted at use).
+  auto load_a = [&](Tin (&buf)[MT][8], const Odo& z) {
 #pragma unroll
     for (int m = 0; m < MT; ++m) {
       const int64_t row = a0 + 16 * m + n;
       const bool rv = row < a.n_rows;
-      const int64_t base = off + row * a.s_row + f0 * a.s_f;
+      const int64_t base = z.off + row * a.s_row + f0 * a.s_f;
       if constexpr (KVEC) {
         if constexpr (sizeof(Tin) == 4) {
 #pragma unroll
@@ -174,10 +189,10 @@ __global__ __launch_bounds__(512) void sketch_kernel(SketchArgs a) {
             const int kk = 4 * g + 16 * h;
             float4 q = make_float4(0.f, 0.f, 0.f, 0.f);
             if (rv && f0 + kk < a.n_f) q = *reinterpret_cast<const float4*>(X + base + kk);
-            av[m][4 * h + 0] = (T)q.x;
-            av[m][4 * h + 1] = (T)q.y;
-            av[m][4 * h + 2] = (T)q.z;
-            av[m][4 * h + 3] = (T)q.w;
+            buf[m][4 * h + 0] = q.x;
+            buf[m][4 * h + 1] = q.y;
+            buf[m][4 * h + 2] = q.z;
+            buf[m][4 * h + 3] = q.w;
           }
         } else {
 #pragma unroll
@@ -185,8 +200,8 @@ __global__ __launch_bounds__(512) void sketch_kernel(SketchArgs a) {
             const int kk = 2 * g + 8 * h;
             double2 q = make_double2(0.0, 0.0);
             if (rv && f0 + kk < a.n_f) q = *reinterpret_cast<const double2*>(X + base + kk);
-            av[m][2 * h + 0] = (T)q.x;
-            av[m][2 * h + 1] = (T)q.y;
+            buf[m][2 * h + 0] = q.x;
+            buf[m][2 * h + 1] = q.y;
           }
         }
       } else {
@@ -195,25 +210,59 @@ __global__ __launch_bounds__(512) void sketch_kernel(SketchArgs a) {
           const int kk = 8 * g + j;
           Tin v = (Tin)0;
           if (rv && f0 + kk < a.n_f) v = X[base + (int64_t)kk * a.s_f];
-          av[m][j] = (T)v;
+          buf[m][j] = v;
         }
       }
     }
-
+  };
+  // Multiply the buffered slice of step z into the accumulators.
+  auto compute = [&](const Tin (&buf)[MT][8], const Odo& z) {
+    T w[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) w[t] = (T)1;
+#pragma unroll
+    for (int k = 0; k < kMaxDims; ++k) {
+      if (k < a.n_out) {
+        const int rr = toff[k] + (int)((z.dig[k] - lo[k] + a.o_size[k]) % a.o_size[k]);
+#pragma unroll
+        for (int t = 0; t < NT; ++t) w[t] = w[t] * tab[rr * CP + 16 * t + n];
+      }
+    }
     typename Pol::Frag bf[NT];
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
       T v[8];
 #pragma unroll
-      for (int j = 0; j < 8; ++j) v[j] = wf[t][j] * w[t];
+      for (int j = 0; j < 8; ++j) v[j] = tab[kmap<Tin, KVEC>(g, j) * CP + 16 * t + n] * w[t];
       bf[t] = Pol::make(v);
     }
 #pragma unroll
     for (int m = 0; m < MT; ++m) {
-      const typename Pol::Frag af = Pol::make(av[m]);
+      T v[8];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) v[j] = (T)buf[m][j];
+      const typename Pol::Frag af = Pol::make(v);
 #pragma unroll
       for (int t = 0; t < NT; ++t) Pol::mma(acc[m][t], af, bf[t]);
     }
+  };
+
+  // Software pipeline: the loads of step o + wo are in flight while step o is
+  // multiplied (two register buffers, alternating).
+  Tin bufA[MT][8], bufB[MT][8];
+  Odo cur = odo_init(o_begin + w_o);
+  if (cur.o < o_end) load_a(bufA, cur);
+  while (cur.o < o_end) {
+    Odo nxt = cur;
+    odo_step(nxt, a.wo);
+    if (nxt.o < o_end) load_a(bufB, nxt);
+    compute(bufA, cur);
+    cur = nxt;
+    if (cur.o >= o_end) break;
+    odo_step(nxt, a.wo);
+    if (nxt.o < o_end) load_a(bufA, nxt);
+    compute(bufB, cur);
+    cur = nxt;
   }
 
 #pragma unroll
@@ -228,36 +277,65 @@ __global__ __launch_bounds__(512) void sketch_kernel(SketchArgs a) {
     }
 }
 
-// Y[a, c] = sum_p partial[chunk(c)][p][a][c mod CP], summed in fp64 in the
-// fixed order p = 0, 1, ...
+// Y[a, c] = sum_p partial[z][p][a][c mod CP] (z = c / CP), summed in fp64.
+// A workgroup owns kRedRows rows of one column chunk; its threads are split
+// into `tpe` groups that sum interleaved subsets of the partials, combined in
+// LDS in a fixed order, so the result does not depend on scheduling.
+constexpr int kRedThreads = 512;
+constexpr int kRedRows = 1;
+
 template <typename AccT>
-__global__ void sketch_reduce_kernel(const AccT* __restrict__ partial, int nparts, int64_t n_rows,
-                                     int ell, int cp, double* __restrict__ y64, void* yout,
-                                     int out_double) {
-  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= n_rows * ell) return;
-  const int64_t a = idx / ell;
-  const int c = (int)(idx - a * ell);
-  const int z = c / cp, cc = c - z * cp;
+__global__ __launch_bounds__(kRedThreads) void sketch_reduce_kernel(
+    const AccT* __restrict__ partial, int nparts, int64_t n_rows, int ell, int cp,
+    double* __restrict__ y64, void* yout, int out_double) {
+  __shared__ double red[kRedThreads];
+  const int z = blockIdx.y;
+  const int64_t r0 = (int64_t)blockIdx.x * kRedRows;
+  const int E = kRedRows * cp;        // elements of this block (<= 64)
+  const int tpe = kRedThreads / E;    // threads per element (>= 8)
+  const int t = threadIdx.x;
+  const int e = t % E, sub = t / E;
+  const int64_t a = r0 + e / cp;
+  const int cc = e % cp;
   const int64_t stride = n_rows * cp;
-  const AccT* p = partial + (int64_t)z * nparts * stride + a * cp + cc;
-  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-  int q = 0;
-  for (; q + 4 <= nparts; q += 4) {
-    s0 += (double)p[(int64_t)(q + 0) * stride];
-    s1 += (double)p[(int64_t)(q + 1) * stride];
-    s2 += (double)p[(int64_t)(q + 2) * stride];
-    s3 += (double)p[(int64_t)(q + 3) * stride];
+  double s = 0.0;
+  if (sub < tpe && a < n_rows) {
+    const AccT* p = partial + (int64_t)z * nparts * stride + a * cp + cc;
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    int q = sub;
+    for (; q + 7 * tpe < nparts; q += 8 * tpe) {
+      const double v0 = (double)p[(int64_t)q * stride];
+      const double v1 = (double)p[(int64_t)(q + tpe) * stride];
+      const double v2 = (double)p[(int64_t)(q + 2 * tpe) * stride];
+      const double v3 = (double)p[(int64_t)(q + 3 * tpe) * stride];
+      const double v4 = (double)p[(int64_t)(q + 4 * tpe) * stride];
+      const double v5 = (double)p[(int64_t)(q + 5 * tpe) * stride];
+      const double v6 = (double)p[(int64_t)(q + 6 * tpe) * stride];
+      const double v7 = (double)p[(int64_t)(q + 7 * tpe) * stride];
+      s0 += v0 + v4;
+      s1 += v1 + v5;
+      s2 += v2 + v6;
+      s3 += v3 + v7;
+    }
+    for (; q < nparts; q += tpe) s0 += (double)p[(int64_t)q * stride];
+    s = (s0 + s1) + (s2 + s3);
   }
-  for (; q < nparts; ++q) s0 += (double)p[(int64_t)q * stride];
-  const double s = (s0 + s1) + (s2 + s3);
-  const int64_t o = a + n_rows * c;
-  if (y64) y64[o] = s;
-  if (yout) {
-    if (out_double)
-      reinterpret_cast<double*>(yout)[o] = s;
-    else
-      reinterpret_cast<float*>(yout)[o] = (float)s;
+  red[t] = s;
+  __syncthreads();
+  if (sub == 0 && a < n_rows) {
+    double tot = red[e];
+    for (int k = 1; k < tpe; ++k) tot += red[e + k * E];
+    const int c = z * cp + cc;
+    if (c < ell) {
+      const int64_t o = a + n_rows * c;
+      if (y64) y64[o] = tot;
+      if (yout) {
+        if (out_double)
+          reinterpret_cast<double*>(yout)[o] = tot;
+        else
+          reinterpret_cast<float*>(yout)[o] = (float)tot;
+      }
+    }
   }
 }
 
@@ -351,6 +429,9 @@ SketchPlan plan_sketch(const SketchProblem& pb, const SketchTile& tile) {
   int mt = tile.mt;
   if (mt != 1 && mt != 2) mt = 4;
   while (mt > 1 && 16 * (mt / 2) >= p.n_rows) mt /= 2;
+  // Scalar (strided) loads need one 64-bit address per element: keep the
+  // register budget within two waves per SIMD by halving the row tiles.
+  if (i == 0 && mt > 2) mt = 2;
   if (fp64 && mt > 2 && p.nt >= 3) mt = 2;  // register budget of fp64 fragments
   p.mt = mt;
   const int64_t wave_rows = 16 * mt;
@@ -438,15 +519,13 @@ hipError_t launch_sketch(const SketchProblem& pb, const SketchPlan& p, void* par
     }
   }
   if (e != hipSuccess) return e;
-  const int64_t nout = p.n_rows * pb.ell;
-  const int rt = 256;
-  const unsigned rg = (unsigned)((nout + rt - 1) / rt);
+  const dim3 rg((unsigned)((p.n_rows + kRedRows - 1) / kRedRows), (unsigned)p.col_chunks);
   if (pb.prec == kFP64)
-    hipLaunchKernelGGL(sketch_reduce_kernel<double>, dim3(rg), dim3(rt), 0, st,
+    hipLaunchKernelGGL(sketch_reduce_kernel<double>, rg, dim3(kRedThreads), 0, st,
                        reinterpret_cast<const double*>(partial), p.nparts, p.n_rows, pb.ell, p.cpad,
                        y64, y_out, out_is_double);
   else
-    hipLaunchKernelGGL(sketch_reduce_kernel<float>, dim3(rg), dim3(rt), 0, st,
+    hipLaunchKernelGGL(sketch_reduce_kernel<float>, rg, dim3(kRedThreads), 0, st,
                        reinterpret_cast<const float*>(partial), p.nparts, p.n_rows, pb.ell, p.cpad,
                        y64, y_out, out_is_double);
   return hipGetLastError();

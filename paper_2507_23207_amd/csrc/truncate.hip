@@ -15,13 +15,14 @@ namespace krp {
 namespace {
 
 constexpr int kEigThreads = 256;
+constexpr int kGramThreads = 256;
 constexpr int kEigMax = 64;
 
 // Gram matrix of mode `mode` of a fp64 tensor viewed as [P][l][Q]:
 // gram[a + l b] = sum_{p,q} g[p, a, q] g[p, b, q].  One block per pair a <= b.
 __global__ void mode_gram_kernel(const double* __restrict__ g, int64_t P, int l, int64_t Q,
                                  double* __restrict__ gram) {
-  __shared__ double red[kEigThreads / 64];
+  __shared__ double red[kGramThreads / 64];
   int pair = blockIdx.x;
   int b = 0;
   while ((b + 1) * (b + 2) / 2 <= pair) ++b;
@@ -43,128 +44,187 @@ __global__ void mode_gram_kernel(const double* __restrict__ g, int64_t P, int l,
   }
 }
 
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Cyclic Jacobi with the round-robin ("chess tournament") ordering: in every
+// round the np/2 disjoint pairs (p, q) are rotated at once.  A round reads
+// A_cur and writes A_next = J^T A_cur J block by block (every 2x2 block
+// {p1, q1} x {p2, q2} of A_next depends only on the same block of A_cur and
+// the two rotations).  Every wave computes the round's rotations itself (so
+// a round needs one workgroup barrier); pair indices are recomputed from the
+// round number; each thread owns one row pair k1 (and one pair of V's
+// columns) and loads every input of its tasks before it stores any result.
+// Sweeps stop when the off-diagonal Frobenius norm is below 1e-13 of the
+// diagonal's.
+constexpr int kJBlocks = 4;  // block tasks per thread: ceil(32 / (256 / 32))
+constexpr int kJVtasks = 8;  // V tasks per thread: ceil(64 / (256 / 32))
+
+// Pair k of round `round` in the round-robin schedule over np indices.
+__device__ __forceinline__ void jacobi_pair(int round, int k, int np, int& p, int& q) {
+  const int m = np - 1;
+  if (k == 0) {
+    p = m;
+    q = round;
+  } else {
+    p = round + k;
+    if (p >= m) p -= m;
+    q = round - k;
+    if (q < 0) q += m;
+  }
+  if (p > q) {
+    const int t = p;
+    p = q;
+    q = t;
+  }
+}
+
 __global__ __launch_bounds__(kEigThreads) void jacobi_eig_kernel(int ell, int r, const double* a_in,
                                                                  int64_t a_stride, double* w,
                                                                  int64_t w_stride, double* evals,
                                                                  int64_t ev_stride) {
-  __shared__ double A[kEigMax * kEigMax];
-  __shared__ double V[kEigMax * kEigMax];
-  __shared__ double cs[kEigMax / 2], sn[kEigMax / 2];
-  __shared__ int pp[kEigMax / 2], qq[kEigMax / 2];
-  __shared__ double red[kEigThreads / 64];
+  constexpr int P = kEigMax + 1;
+  constexpr int NW = kEigThreads / 64;
+  __shared__ double A[2][kEigMax * P];
+  __shared__ double V[kEigMax * P];
+  __shared__ double2 rcs[NW][kEigMax / 2];
+  __shared__ double red[2][NW];
   __shared__ int order_idx[kEigMax];
-  __shared__ int done;
 
   const int b = blockIdx.x;
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int np = ell + (ell & 1);
+  const int half = np / 2;
+  const int cpp = kEigThreads / half;  // thread columns per pass (>= 8)
+  const bool active = tid < half * cpp;
+  const int k1 = tid % half, kb = tid / half;
   const double* ain = a_in + b * a_stride;
   for (int e = tid; e < np * np; e += kEigThreads) {
     const int i = e % np, j = e / np;
     double v = 0.0;
     if (i < ell && j < ell) v = ain[i + (int64_t)ell * j];
     else if (i == j) v = -1.0;  // padding index: decoupled, sorts last (the input is PSD)
-    A[i + np * j] = v;
-    V[i + np * j] = (i == j) ? 1.0 : 0.0;
+    A[0][i * P + j] = v;
+    V[i * P + j] = (i == j) ? 1.0 : 0.0;
   }
   __syncthreads();
-  const int half = np / 2;
-  for (int sweep = 0; sweep < 40; ++sweep) {
-    // convergence: sum of squared off-diagonal entries against the diagonal
+  int cur = 0;
+  for (int sweep = 0; sweep < 60; ++sweep) {
     double off = 0.0, dia = 0.0;
     for (int e = tid; e < np * np; e += kEigThreads) {
       const int i = e % np, j = e / np;
-      const double v = A[e];
+      const double v = A[cur][i * P + j];
       if (i != j) off += v * v;
       else dia += v * v;
     }
     off = wave_sum(off);
     dia = wave_sum(dia);
-    if ((tid & 63) == 0) red[tid >> 6] = off;
-    __syncthreads();
-    if (tid == 0) {
-      double t = 0.0;
-      for (int k = 0; k < kEigThreads / 64; ++k) t += red[k];
-      red[0] = t;
+    if (lane == 0) {
+      red[0][wave] = off;
+      red[1][wave] = dia;
     }
     __syncthreads();
-    const double off_all = red[0];
-    __syncthreads();
-    if ((tid & 63) == 0) red[tid >> 6] = dia;
-    __syncthreads();
-    if (tid == 0) {
-      double t = 0.0;
-      for (int k = 0; k < kEigThreads / 64; ++k) t += red[k];
-      done = (off_all <= 1e-30 * t) ? 1 : 0;
+    double to = 0.0, td = 0.0;
+    for (int k = 0; k < NW; ++k) {
+      to += red[0][k];
+      td += red[1][k];
     }
     __syncthreads();
-    if (done) break;
+    if (to <= 1e-26 * td) break;
     for (int round = 0; round < np - 1; ++round) {
-      if (tid < half) {
+      const double* Ac = A[cur];
+      double* An = A[cur ^ 1];
+      if (lane < half) {
         int p, q;
-        if (tid == 0) {
-          p = np - 1;
-          q = round;
-        } else {
-          p = (round + tid) % (np - 1);
-          q = (round - tid + np - 1) % (np - 1);
-        }
-        if (p > q) {
-          const int t = p;
-          p = q;
-          q = t;
-        }
-        const double apq = A[p + np * q];
+        jacobi_pair(round, lane, np, p, q);
+        const double apq = Ac[p * P + q];
+        const double app = Ac[p * P + p], aqq = Ac[q * P + q];
         double c = 1.0, s = 0.0;
         if (apq != 0.0) {
-          const double app = A[p + np * p], aqq = A[q + np * q];
           const double theta = (aqq - app) / (2.0 * apq);
           const double t = (theta >= 0.0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
           c = 1.0 / sqrt(t * t + 1.0);
           s = t * c;
         }
-        pp[tid] = p;
-        qq[tid] = q;
-        cs[tid] = c;
-        sn[tid] = s;
+        rcs[wave][lane] = make_double2(c, s);
+      }
+      wave_sync();
+      if (active) {
+        int p1, q1;
+        jacobi_pair(round, k1, np, p1, q1);
+        const double2 r1 = rcs[wave][k1];
+        int p2[kJBlocks], q2[kJBlocks], pv[kJVtasks];
+        double2 r2[kJBlocks];
+        double bb[kJBlocks][4], v0[kJVtasks], v1[kJVtasks];
+        // loads
+#pragma unroll
+        for (int u = 0; u < kJBlocks; ++u) {
+          const int k2 = kb + u * cpp;
+          if (k2 < half) {
+            jacobi_pair(round, k2, np, p2[u], q2[u]);
+            r2[u] = rcs[wave][k2];
+            bb[u][0] = Ac[p1 * P + p2[u]];
+            bb[u][1] = Ac[p1 * P + q2[u]];
+            bb[u][2] = Ac[q1 * P + p2[u]];
+            bb[u][3] = Ac[q1 * P + q2[u]];
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < kJVtasks; ++u) {
+          const int i = kb + u * cpp;
+          if (i < np) {
+            pv[u] = i * P;
+            v0[u] = V[pv[u] + p1];
+            v1[u] = V[pv[u] + q1];
+          }
+        }
+        // rotations and stores
+#pragma unroll
+        for (int u = 0; u < kJBlocks; ++u) {
+          const int k2 = kb + u * cpp;
+          if (k2 < half) {
+            const double c2 = r2[u].x, s2 = r2[u].y, c1 = r1.x, s1 = r1.y;
+            const double t00 = c2 * bb[u][0] - s2 * bb[u][1], t01 = s2 * bb[u][0] + c2 * bb[u][1];
+            const double t10 = c2 * bb[u][2] - s2 * bb[u][3], t11 = s2 * bb[u][2] + c2 * bb[u][3];
+            double n00 = c1 * t00 - s1 * t10, n01 = c1 * t01 - s1 * t11;
+            double n10 = s1 * t00 + c1 * t10, n11 = s1 * t01 + c1 * t11;
+            if (k2 == k1) {
+              n01 = 0.0;
+              n10 = 0.0;
+            }
+            An[p1 * P + p2[u]] = n00;
+            An[p1 * P + q2[u]] = n01;
+            An[q1 * P + p2[u]] = n10;
+            An[q1 * P + q2[u]] = n11;
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < kJVtasks; ++u) {
+          const int i = kb + u * cpp;
+          if (i < np) {
+            V[pv[u] + p1] = r1.x * v0[u] - r1.y * v1[u];
+            V[pv[u] + q1] = r1.y * v0[u] + r1.x * v1[u];
+          }
+        }
       }
       __syncthreads();
-      // A <- A J (columns p, q of every row)
-      for (int e = tid; e < np * half; e += kEigThreads) {
-        const int i = e % np, k = e / np;
-        const int p = pp[k], q = qq[k];
-        const double c = cs[k], s = sn[k];
-        const double aip = A[i + np * p], aiq = A[i + np * q];
-        A[i + np * p] = c * aip - s * aiq;
-        A[i + np * q] = s * aip + c * aiq;
-      }
-      __syncthreads();
-      // A <- J^T A (rows p, q of every column) and V <- V J
-      for (int e = tid; e < np * half; e += kEigThreads) {
-        const int i = e % np, k = e / np;
-        const int p = pp[k], q = qq[k];
-        const double c = cs[k], s = sn[k];
-        const double api = A[p + np * i], aqi = A[q + np * i];
-        A[p + np * i] = c * api - s * aqi;
-        A[q + np * i] = s * api + c * aqi;
-        const double vip = V[i + np * p], viq = V[i + np * q];
-        V[i + np * p] = c * vip - s * viq;
-        V[i + np * q] = s * vip + c * viq;
-      }
-      __syncthreads();
+      cur ^= 1;
     }
   }
-  if (tid == 0) {
-    // descending eigenvalues (stable: ties keep the lower index first)
-    for (int i = 0; i < np; ++i) order_idx[i] = i;
-    for (int i = 0; i < np; ++i) {
-      int best = i;
-      for (int j = i + 1; j < np; ++j)
-        if (A[order_idx[j] * (np + 1)] > A[order_idx[best] * (np + 1)]) best = j;
-      const int t = order_idx[i];
-      order_idx[i] = order_idx[best];
-      order_idx[best] = t;
+  // descending eigenvalues by ranking (ties keep the lower index first)
+  if (tid < np) order_idx[tid] = tid;
+  __syncthreads();
+  if (tid < np) {
+    const double li = A[cur][tid * (P + 1)];
+    int rank = 0;
+    for (int j = 0; j < np; ++j) {
+      const double lj = A[cur][j * (P + 1)];
+      rank += (lj > li || (lj == li && j < tid)) ? 1 : 0;
     }
+    order_idx[rank] = tid;
   }
   __syncthreads();
   double* wout = w + b * w_stride;
@@ -173,15 +233,15 @@ __global__ __launch_bounds__(kEigThreads) void jacobi_eig_kernel(int ell, int r,
     int imax = 0;
     double vmax = -1.0;
     for (int i = 0; i < ell; ++i) {
-      const double v = fabs(V[i + np * c]);
+      const double v = fabs(V[i * P + c]);
       if (v > vmax) {
         vmax = v;
         imax = i;
       }
     }
-    const double sgn = V[imax + np * c] < 0.0 ? -1.0 : 1.0;
-    for (int i = 0; i < ell; ++i) wout[i + (int64_t)ell * j] = sgn * V[i + np * c];
-    if (evals) evals[b * ev_stride + j] = A[c * (np + 1)];
+    const double sgn = V[imax * P + c] < 0.0 ? -1.0 : 1.0;
+    for (int i = 0; i < ell; ++i) wout[i + (int64_t)ell * j] = sgn * V[i * P + c];
+    if (evals) evals[b * ev_stride + j] = A[cur][c * (P + 1)];
   }
 }
 
@@ -266,7 +326,7 @@ hipError_t launch_truncate(const TruncPlan& p, const void* core, int core_double
     for (int k = i + 1; k < d; ++k) Q *= cur[k];
     const int l = (int)cur[i];
     const int npairs = l * (l + 1) / 2;
-    hipLaunchKernelGGL(mode_gram_kernel, dim3(npairs), dim3(kEigThreads), 0, st, g[s & 1], P, l, Q, gram);
+    hipLaunchKernelGGL(mode_gram_kernel, dim3(npairs), dim3(kGramThreads), 0, st, g[s & 1], P, l, Q, gram);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     double* wi = reinterpret_cast<double*>(ws + p.off_w[i]);
