@@ -1,12 +1,18 @@
 // Thin QR of tall-skinny sketches (Algorithm 7, step 4; Algorithm 8, step 5;
 // Algorithm 6, step 3) by CholeskyQR2 in fp64, one workgroup per matrix:
-//   G = Y^T Y,  R = chol(G) (upper, positive diagonal),  Q = Y R^{-1},
-// repeated once on Q.  The Gram matrix and the product Y R^{-1} run on the
-// fp64 matrix cores (16x16x4 tiles); the Cholesky factor and R^{-1} are formed
-// by one wavefront in LDS (one lane per column).  A pivot that is
-// non-positive, non-finite or below 1e-14 of its column's squared norm marks Y
-// as too ill-conditioned for the Gram route; that pass is then redone on
-// G + s I with s = 11 (n l + l (l + 1)) 2^-53 ||Y||_F^2 (shifted CholeskyQR,
+//   G = Y^T Y,  G = R^T R (R upper, positive diagonal),  Q = Y R^{-1},
+// repeated once on Q.  Y streams through LDS in coalesced chunks of rows (the
+// next chunk is loaded while the current one is processed); the Gram tiles
+// and the products with R^{-1} run on the fp64 matrix cores (16x16x4), and
+// the Gram matrix of the second pass is accumulated from the chunks of the
+// first pass's Q as they are written.  R^{-1} comes from symmetric Gaussian
+// elimination G = L D L^T applied to the rows of [I | G]: after the
+// elimination the left part holds L^{-1} and the right part U = D L^T, and
+// R^{-1} = L^{-T} D^{-1/2}; every thread owns a piece of a row, so a step is
+// one rank-one row update and one workgroup barrier.  A pivot that is
+// non-positive, non-finite or below 1e-14 of its (shifted) diagonal entry
+// marks Y as too ill-conditioned for the Gram route; that pass is then redone
+// on G + s I with s = 11 (n l + l (l + 1)) 2^-53 ||Y||_F^2 (shifted CholeskyQR,
 // Fukaya et al. 2020) and followed by two unshifted passes (shifted
 // CholeskyQR3).  Since diag(R) > 0 the result equals the Householder Q whose
 // R has a positive diagonal.
@@ -19,243 +25,265 @@ namespace {
 
 constexpr int kQrMaxEll = 64;
 constexpr int kQrWaves = 8;
-constexpr int kQrMaxTasks = 16;  // Gram tile tasks (<= 10 tiles x splits)
 constexpr int kQrThreads = 64 * kQrWaves;
-constexpr int kGp = kQrMaxEll + 1;  // LDS pitch of the l x l matrices
+constexpr int kQrCh = 64;                 // rows per streamed chunk
+constexpr int kQrPitch = kQrMaxEll + 1;   // pitch of chunks, G and R^{-1}
+constexpr int kQrCPitch = kQrMaxEll + 2;  // pitch of the combined rows (ell + 1 columns)
+constexpr int kQrMaxTasks = 16;           // matrix-core tasks (<= 2 per wave)
+constexpr int kQrColsPerThread = 9;       // ceil(65 / 8): combined columns per thread
 
 struct QrShared {
-  double g[kQrMaxEll * kGp];        // Gram, then R (upper triangle)
-  double rinv[kQrMaxEll * kGp];     // R^{-1} (upper triangle, zeros below)
-  double part[kQrMaxTasks * 256];   // 16x16 Gram tile partials per task
-  double orig_diag[kQrMaxEll];
-  int fail;
+  double chunk_in[kQrCh * kQrPitch];   // rows of the streamed matrix (row-major); Gram partials at the end
+  double chunk_out[kQrCh * kQrPitch];  // rows of the product with R^{-1} (row-major)
+  double c[kQrMaxEll * kQrCPitch];     // combined rows [L^{-1} | U] of the elimination
+  double g[kQrMaxEll * kQrPitch];      // Gram matrix; after a successful elimination R^{-1}
+  double diag_ref[kQrMaxEll];
+  double tr;
 };
 
 using Pol = Policy<kFP64>;
 
-// G = src^T src (src: n x l column-major, fp64) on the matrix cores.  Tiles
-// (ti <= tj) of 16x16 are split over the waves along the rows of src.
-__device__ void qr_gram(const double* src, int64_t n, int ell, QrShared& sh) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+__device__ __forceinline__ void tile_pair(int T, int pair, int& ti, int& tj) {
+  int cnt = 0;
+  ti = 0;
+  tj = 0;
+  for (int a = 0; a < T; ++a)
+    for (int b = a; b < T; ++b) {
+      if (cnt == pair) {
+        ti = a;
+        tj = b;
+      }
+      ++cnt;
+    }
+}
+
+// Streams rows of src (n x ell, fp64, column-major) through LDS in chunks of
+// kQrCh rows.  APPLY: dst = src R^{-1} (R^{-1} in sh.g), written to dst (and
+// q_out when FINAL).  GRAM: G of the streamed rows (of dst when APPLY) into
+// sh.g (after the stream; both triangles).  dst may alias src: every chunk is
+// read completely before any of its rows is written.
+template <bool APPLY, bool GRAM, bool FINAL>
+__device__ void qr_stream(const double* src, double* dst, int64_t n, int ell, void* q_out,
+                          int out_double, QrShared& sh) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int nl = lane & 15, g = lane >> 4;
   const int T = (ell + 15) / 16;
-  const int ntiles = T * (T + 1) / 2;
-  const int ks = ntiles >= kQrWaves ? 1 : kQrWaves / ntiles;  // row splits per tile
-  for (int task = wave; task < ntiles * ks; task += kQrWaves) {
-    const int tile = task % ntiles, kpart = task / ntiles;
-    int ti = 0, tj = 0, cnt = 0;
-    for (int a = 0; a < T; ++a)
-      for (int b = a; b < T; ++b) {
-        if (cnt == tile) {
-          ti = a;
-          tj = b;
-        }
-        ++cnt;
-      }
-    const int64_t chunk = ((n + ks - 1) / ks + 31) / 32 * 32;
-    const int64_t r0 = kpart * chunk, r1 = min(n, r0 + chunk);
-    const int ca = 16 * ti + nl, cb = 16 * tj + nl;
-    Pol::Acc acc = Pol::zero();
-#pragma unroll 4
-    for (int64_t k0 = r0; k0 < r1; k0 += 32) {
-      double av[8], bv[8];
+  const int lp = 16 * T;
+  // Gram tasks: tile pairs (ti <= tj) x splits of the chunk's 16 row quads
+  const int pairs = T * (T + 1) / 2;
+  const int ks = pairs == 1 ? 16 : pairs <= 3 ? 4 : pairs <= 6 ? 2 : 1;
+  const int gtasks = pairs * ks;
+  const int qper = 16 / ks;
+  // chunk loads: row r, columns cg + 8 j
+  const int lr = tid % kQrCh, cg = tid / kQrCh;
+  const int nch = (int)((n + kQrCh - 1) / kQrCh);
+  Pol::Acc gacc[2];
+  gacc[0] = Pol::zero();
+  gacc[1] = Pol::zero();
+  double pre[8];
+  auto load_chunk = [&](int ch) {
+    const int64_t row = (int64_t)ch * kQrCh + lr;
 #pragma unroll
-      for (int j = 0; j < 8; ++j) {
-        const int64_t k = k0 + 8 * g + j;
-        const bool kv = k < r1;
-        av[j] = (kv && ca < ell) ? src[k + n * ca] : 0.0;
-        bv[j] = (kv && cb < ell) ? src[k + n * cb] : 0.0;
-      }
-      Pol::mma(acc, Pol::make(av), Pol::make(bv));
+    for (int j = 0; j < 8; ++j) {
+      const int c = cg + 8 * j;
+      pre[j] = (row < n && c < ell) ? src[row + n * c] : 0.0;
     }
+  };
+  load_chunk(0);
+  for (int ch = 0; ch < nch; ++ch) {
+    // store the prefetched rows (columns up to lp, zeros past ell and n)
 #pragma unroll
-    for (int r = 0; r < 4; ++r) sh.part[task * 256 + Pol::out_row(g, r) * 16 + nl] = acc[r];
-  }
-  __syncthreads();
-  // sum the row splits of every tile into g (both triangles)
-  for (int e = threadIdx.x; e < ntiles * 256; e += kQrThreads) {
-    const int tile = e / 256, w = e % 256;
-    const int i = w / 16, j = w % 16;
-    int ti = 0, tj = 0, cnt = 0;
-    for (int a = 0; a < T; ++a)
-      for (int b = a; b < T; ++b) {
-        if (cnt == tile) {
-          ti = a;
-          tj = b;
-        }
-        ++cnt;
-      }
-    double s = 0.0;
-    for (int k = 0; k < ks; ++k) s += sh.part[(tile + ntiles * k) * 256 + i * 16 + j];
-    const int gi = 16 * ti + i, gj = 16 * tj + j;
-    if (gi < ell && gj < ell) {
-      sh.g[gi * kGp + gj] = s;
-      sh.g[gj * kGp + gi] = s;
+    for (int j = 0; j < 8; ++j) {
+      const int c = cg + 8 * j;
+      if (c < lp) sh.chunk_in[lr * kQrPitch + c] = pre[j];
     }
-  }
-  __syncthreads();
-}
-
-// Upper Cholesky of g (+ shift on the diagonal) and R^{-1}, by wave 0 only.
-// Lane j keeps column j in registers (loops unrolled over the 64 possible
-// rows, masked by ell); the row of R needed at each step is broadcast through
-// a separate LDS buffer, so every read of a step can be issued at once.  Sets
-// sh.fail on breakdown.  Ends with a workgroup barrier.
-__device__ __forceinline__ void wave_sync_lds() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
-__device__ __noinline__ void qr_rinv(int ell, QrShared& sh);
-
-__device__ __noinline__ void qr_chol(int ell, double shift, QrShared& sh) {
-  if (threadIdx.x < 64) {
-    const int j = threadIdx.x;
-    const bool jv = j < ell;
-    double* bc = sh.orig_diag;  // 64-entry broadcast buffer
-    double col[kQrMaxEll];
+    if (ch + 1 < nch) load_chunk(ch + 1);
+    __syncthreads();
+    const double* gsrc = sh.chunk_in;
+    if (APPLY) {
+      // 64 x lp output tiles (row tile rt, column tile tc); R^{-1} is upper
+      // triangular, so column tile tc only needs k < 16 tc + 16
+#pragma unroll 1
+      for (int tile = wave; tile < 4 * T; tile += kQrWaves) {
+        const int rt = tile & 3, tc = tile >> 2;
+        Pol::Acc acc = Pol::zero();
+        // k < 16 tc + 16: 4 tc + 4 steps of four, in groups of 8 whose
+        // operands are all read before the group's products
+#pragma unroll 1
+        for (int s0 = 0; s0 < 4 * tc + 4; s0 += 8) {
+          double av[8], bv[8];
 #pragma unroll
-    for (int i = 0; i < kQrMaxEll; ++i) col[i] = (jv && i < ell) ? sh.g[i * kGp + j] : 0.0;
-    double ref = 0.0;
-#pragma unroll
-    for (int i = 0; i < kQrMaxEll; ++i)
-      if (i == j) {
-        ref = col[i] + shift;
-        col[i] = ref;
-      }
-    int fail = 0;
-#pragma unroll
-    for (int k = 0; k < kQrMaxEll; ++k) {
-      if (k < ell) {
-        if (j == k) {
-          double d = col[k];
-          if (!(d > 1e-14 * ref) || !isfinite(d)) {
-            fail = 1;
-            d = 1.0;
+          for (int s = 0; s < 8; ++s) {
+            const int k = 4 * (s0 + s) + g;
+            av[s] = sh.chunk_in[(16 * rt + nl) * kQrPitch + k];
+            bv[s] = sh.g[k * kQrPitch + 16 * tc + nl];
           }
-          col[k] = sqrt(d);
-          bc[k] = col[k];
+#pragma unroll
+          for (int s = 0; s < 8; ++s)
+            if (s0 + s < 4 * tc + 4) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[s], bv[s], acc, 0, 0, 0);
         }
-        wave_sync_lds();
-        const double rkk = bc[k];
-        if (j > k) col[k] /= rkk;
-        wave_sync_lds();
-        bc[j] = col[k];  // row k of R (entries j > k)
-        wave_sync_lds();
-        if (j > k && jv) {
-          const double rkj = col[k];
 #pragma unroll
-          for (int i = k + 1; i < kQrMaxEll; ++i) col[i] -= bc[i] * rkj;
-        }
-        wave_sync_lds();
+        for (int r = 0; r < 4; ++r)
+          sh.chunk_out[(16 * rt + Pol::out_row(g, r)) * kQrPitch + 16 * tc + nl] = acc[r];
       }
-    }
+      __syncthreads();
+      const int64_t row = (int64_t)ch * kQrCh + lr;
+      if (row < n) {
 #pragma unroll
-    for (int i = 0; i < kQrMaxEll; ++i)
-      if (jv && i <= j) sh.g[i * kGp + j] = col[i];
-    fail = __any(fail);
-    if (j == 0) sh.fail = fail;
-  }
-}
-
-__device__ __noinline__ void qr_rinv(int ell, QrShared& sh) {
-  if (threadIdx.x < 64) {
-    const int j = threadIdx.x;
-    const bool jv = j < ell;
-    double col[kQrMaxEll];
-    // R^{-1} by rows: lane i holds row i of X = R^{-1} (reusing col), with
-    // X[i][c] = (delta_ic - sum_{k < c} X[i][k] R[k][c]) / R[c][c]; entries
-    // k < i are zero, R[k][c] is read from LDS (same address in every lane).
-#pragma unroll
-    for (int c = 0; c < kQrMaxEll; ++c) col[c] = 0.0;
-#pragma unroll
-    for (int c = 0; c < kQrMaxEll; ++c) {
-      if (c < ell) {
-        double s = (c == j) ? 1.0 : 0.0;
-#pragma unroll
-        for (int k = 0; k < c; ++k) s -= col[k] * sh.g[k * kGp + c];
-        col[c] = (c >= j && jv) ? s / sh.g[c * kGp + c] : 0.0;
-      }
-    }
-#pragma unroll
-    for (int c = 0; c < kQrMaxEll; ++c)
-      if (jv) sh.rinv[j * kGp + c] = col[c];
-    if (!jv) {
-#pragma unroll
-      for (int c = 0; c < kQrMaxEll; ++c) sh.rinv[j * kGp + c] = 0.0;
-    }
-  }
-  __syncthreads();
-}
-
-__device__ void qr_chol_inv(int ell, double shift, QrShared& sh) {
-  qr_chol(ell, shift, sh);
-  wave_sync_lds();
-  qr_rinv(ell, sh);
-}
-
-// dst = src R^{-1} on the matrix cores: tiles of 16 rows x 16 columns, the
-// reduction over l in slices of 32 (R^{-1} from LDS).  dst may alias src only
-// if every tile reads its rows before writing them, which holds: a wave owns
-// its rows for all column tiles and reads all of them first.
-template <bool FINAL>
-__device__ void qr_apply(const double* src, double* dst, int64_t n, int ell, void* q_out, int out_double,
-                         QrShared& sh) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int nl = lane & 15, g = lane >> 4;
-  const int T = (ell + 15) / 16;
-  const int KS = (ell + 31) / 32;  // reduction slices of 32
-  const int64_t rtiles = (n + 15) / 16;
-  for (int64_t rt = wave; rt < rtiles; rt += kQrWaves) {
-    const int64_t row = rt * 16 + nl;
-    Pol::Acc acc[4];
-    for (int t = 0; t < 4; ++t) acc[t] = Pol::zero();
-    for (int s = 0; s < KS; ++s) {
-      double av[8];
-#pragma unroll
-      for (int j = 0; j < 8; ++j) {
-        const int k = 32 * s + 8 * g + j;
-        av[j] = (row < n && k < ell) ? src[row + n * k] : 0.0;
-      }
-      const Pol::Frag af = Pol::make(av);
-#pragma unroll
-      for (int t = 0; t < 4; ++t) {
-        if (t < T) {
-          double bv[8];
-#pragma unroll
-          for (int j = 0; j < 8; ++j) {
-            const int k = 32 * s + 8 * g + j;
-            const int c = 16 * t + nl;
-            bv[j] = (k < ell && c < ell) ? sh.rinv[k * kGp + c] : 0.0;
-          }
-          Pol::mma(acc[t], af, Pol::make(bv));
-        }
-      }
-    }
-#pragma unroll
-    for (int t = 0; t < 4; ++t) {
-      if (t < T) {
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int64_t rr = rt * 16 + Pol::out_row(g, r);
-          const int c = 16 * t + nl;
-          if (rr < n && c < ell) {
-            const int64_t o = rr + n * c;
-            const double v = acc[t][r];
-            dst[o] = v;
+        for (int j = 0; j < 8; ++j) {
+          const int c = cg + 8 * j;
+          if (c < ell) {
+            const double v = sh.chunk_out[lr * kQrPitch + c];
+            dst[row + n * c] = v;
             if (FINAL && q_out) {
               if (out_double)
-                reinterpret_cast<double*>(q_out)[o] = v;
+                reinterpret_cast<double*>(q_out)[row + n * c] = v;
               else
-                reinterpret_cast<float*>(q_out)[o] = (float)v;
+                reinterpret_cast<float*>(q_out)[row + n * c] = (float)v;
             }
           }
         }
       }
+      // rows past n of the last chunk are zero in chunk_in, hence in chunk_out
+      gsrc = sh.chunk_out;
+    }
+    if (GRAM) {
+#pragma unroll 1
+      for (int u = 0; u < 2; ++u) {
+        const int task = wave + u * kQrWaves;
+        if (task < gtasks) {
+          const int pair = task % pairs, kh = task / pairs;
+          int ti, tj;
+          tile_pair(T, pair, ti, tj);
+          Pol::Acc acc = u ? gacc[1] : gacc[0];
+#pragma unroll 1
+          for (int s0 = 0; s0 < qper; s0 += 8) {
+            double av[8], bv[8];
+#pragma unroll
+            for (int s = 0; s < 8; ++s) {
+              const int q = kh * qper + min(s0 + s, qper - 1);
+              av[s] = gsrc[(4 * q + g) * kQrPitch + 16 * ti + nl];
+              bv[s] = gsrc[(4 * q + g) * kQrPitch + 16 * tj + nl];
+            }
+#pragma unroll
+            for (int s = 0; s < 8; ++s)
+              if (s0 + s < qper) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[s], bv[s], acc, 0, 0, 0);
+          }
+          if (u) gacc[1] = acc;
+          else gacc[0] = acc;
+        }
+      }
+    }
+    __syncthreads();
+  }
+  if (GRAM) {
+    double* part = sh.chunk_in;  // kQrMaxTasks x 256 partial tiles
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int task = wave + u * kQrWaves;
+      if (task < gtasks) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) part[task * 256 + Pol::out_row(g, r) * 16 + nl] = gacc[u][r];
+      }
+    }
+    __syncthreads();
+    for (int e = tid; e < pairs * 256; e += kQrThreads) {
+      const int pair = e / 256, w = e % 256;
+      const int i = w / 16, j = w % 16;
+      int ti, tj;
+      tile_pair(T, pair, ti, tj);
+      double s = 0.0;
+      for (int kh = 0; kh < ks; ++kh) s += part[(pair + pairs * kh) * 256 + i * 16 + j];
+      const int gi = 16 * ti + i, gj = 16 * tj + j;
+      if (gi < ell && gj < ell) {
+        sh.g[gi * kQrPitch + gj] = s;
+        sh.g[gj * kQrPitch + gi] = s;
+      }
+    }
+    __syncthreads();
+    if (tid < 64) {
+      const double d = tid < ell ? sh.g[tid * kQrPitch + tid] : 0.0;
+      const double t = wave_sum(d);
+      if (tid == 0) sh.tr = t;
+    }
+    __syncthreads();
+  }
+}
+
+// R^{-1} of G + shift I into sh.g by symmetric elimination of [I | G] rows.
+// Returns false (uniformly) on a pivot breakdown, leaving sh.g untouched.
+__device__ bool qr_elim(int ell, double shift, QrShared& sh) {
+  const int tid = threadIdx.x;
+  const int tpr = kQrThreads / ell;                // threads per row (>= 8)
+  const int cpt = (ell + 1 + tpr - 1) / tpr;       // combined columns per thread (<= 9)
+  const int row = tid / tpr, sub = tid % tpr;
+  const bool has_row = row < ell;
+  const int c0 = sub * cpt;
+  double cv[kQrColsPerThread];
+  __syncthreads();  // a previous elimination may still be reading sh.c
+  // combined row i: columns c <= i hold L^{-1}[i][c] (identity at first),
+  // columns c > i hold the Schur complement entry (i, c - 1)
+#pragma unroll
+  for (int q = 0; q < kQrColsPerThread; ++q) {
+    const int c = c0 + q;
+    double v = 0.0;
+    if (has_row && q < cpt && c <= ell) {
+      if (c <= row) v = (c == row) ? 1.0 : 0.0;
+      else v = sh.g[row * kQrPitch + c - 1] + ((c - 1 == row) ? shift : 0.0);
+      sh.c[row * kQrCPitch + c] = v;
+    }
+    cv[q] = v;
+  }
+  if (tid < ell) sh.diag_ref[tid] = sh.g[tid * kQrPitch + tid] + shift;
+  __syncthreads();
+  bool ok = true;
+  const int rl = has_row ? row + 1 : 0;
+  for (int k = 0; k < ell; ++k) {
+    // every read of the step is issued before any use
+    const double* ck = &sh.c[k * kQrCPitch];
+    const double piv = ck[k + 1], ref = sh.diag_ref[k], num = ck[rl];
+    double rk[kQrColsPerThread];
+#pragma unroll
+    for (int q = 0; q < kQrColsPerThread; ++q) rk[q] = ck[min(c0 + q, ell)];
+    if (!(piv > 1e-14 * ref) || !isfinite(piv)) {
+      ok = false;
+      break;
+    }
+    if (has_row && row > k) {
+      const double l = num / piv;
+#pragma unroll
+      for (int q = 0; q < kQrColsPerThread; ++q) {
+        const int c = c0 + q;
+        if (q < cpt && c <= ell && (c <= k || c > row)) cv[q] -= l * rk[q];
+      }
+      if (row == k + 1) {
+#pragma unroll
+        for (int q = 0; q < kQrColsPerThread; ++q) {
+          const int c = c0 + q;
+          if (q < cpt && c <= ell) sh.c[row * kQrCPitch + c] = cv[q];
+        }
+      }
+    }
+    __syncthreads();
+  }
+  if (!ok) return false;
+  // R^{-1}[m][i] = L^{-1}[i][m] / sqrt(U[i][i]) for m <= i, zero elsewhere
+  // (including the padding up to the next multiple of 16)
+  if (has_row) {
+    const double dinv = 1.0 / sqrt(sh.c[row * kQrCPitch + row + 1]);
+#pragma unroll
+    for (int q = 0; q < kQrColsPerThread; ++q) {
+      const int c = c0 + q;
+      if (q < cpt && c <= row) sh.g[c * kQrPitch + row] = cv[q] * dinv;
     }
   }
+  const int lp = (ell + 15) / 16 * 16;
+  for (int e = tid; e < lp * lp; e += kQrThreads) {
+    const int m = e / lp, i = e % lp;
+    if (m > i || i >= ell) sh.g[m * kQrPitch + i] = 0.0;
+  }
   __syncthreads();
+  return true;
 }
 
 __global__ __launch_bounds__(kQrThreads) void cholqr_kernel(int64_t n_default, int ell, const double* y,
@@ -271,11 +299,10 @@ __global__ __launch_bounds__(kQrThreads) void cholqr_kernel(int64_t n_default, i
   char* qo = nullptr;
   if (q_out) qo = reinterpret_cast<char*>(q_out) + off * (out_double ? 8 : 4);
 
+  qr_stream<false, true, false>(src, dst, n, ell, nullptr, out_double, sh);
   int clean = 0;  // consecutive unshifted passes
   for (int pass = 0; pass < 6; ++pass) {
-    qr_gram(src, n, ell, sh);
-    double tr = 0.0;
-    for (int k = 0; k < ell; ++k) tr += sh.g[k * kGp + k];
+    const double tr = sh.tr;
     if (!isfinite(tr)) {
       if (threadIdx.x == 0) raise_status(status, kStatNonFinite);
       for (int64_t e = threadIdx.x; e < n * ell; e += kQrThreads) {
@@ -289,28 +316,23 @@ __global__ __launch_bounds__(kQrThreads) void cholqr_kernel(int64_t n_default, i
       }
       return;
     }
-    qr_chol_inv(ell, 0.0, sh);
-    if (!sh.fail) {
+    if (qr_elim(ell, 0.0, sh)) {
       ++clean;
     } else {
       if (threadIdx.x == 0) raise_status(status, kStatCholShift);
-      __syncthreads();
-      qr_gram(src, n, ell, sh);
       const double shift = 11.0 * ((double)n * ell + (double)ell * (ell + 1)) * 0x1.0p-53 * tr;
-      qr_chol_inv(ell, shift, sh);
-      if (sh.fail) {
+      if (!qr_elim(ell, shift, sh)) {
         if (threadIdx.x == 0) raise_status(status, kStatCholFail);
         return;
       }
       clean = 0;
     }
-    const bool last = (clean == 2);
-    if (last)
-      qr_apply<true>(src, dst, n, ell, qo, out_double, sh);
-    else
-      qr_apply<false>(src, dst, n, ell, nullptr, out_double, sh);
+    if (clean == 2) {
+      qr_stream<true, false, true>(src, dst, n, ell, qo, out_double, sh);
+      return;
+    }
+    qr_stream<true, true, false>(src, dst, n, ell, nullptr, out_double, sh);
     src = dst;
-    if (last) return;
   }
   if (threadIdx.x == 0) raise_status(status, kStatCholFail);
 }

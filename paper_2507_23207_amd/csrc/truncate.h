@@ -15,7 +15,7 @@ struct TruncPlan {
   int d = 0;
   int ell[kMaxDims]{}, rank[kMaxDims]{}, order[kMaxDims]{};
   int64_t dims[kMaxDims]{};
-  size_t off_g[2]{}, off_gram = 0, off_w[kMaxDims]{}, off_qt[kMaxDims]{};
+  size_t off_g[2]{}, off_gram[kMaxDims]{}, off_v0[kMaxDims]{}, off_w[kMaxDims]{}, off_qt[kMaxDims]{};
   size_t ws_bytes = 0;
 };
 
@@ -34,8 +34,24 @@ double* truncated_q64(const TruncPlan& p, char* ws, int k);
 // cyclic Jacobi; writes the r leading eigenvectors (descending eigenvalues,
 // each with its largest-magnitude entry positive) to w (ell x r) and the
 // eigenvalues to evals (may be null).  One workgroup per matrix of a batch:
-// matrix b at a + b * lda_stride, output at w + b * w_stride.
+// matrix b at a + b * a_stride, output at w + b * w_stride.  v_init (optional,
+// ell x ell orthogonal, at v_init + b * v_stride) starts the iteration from
+// the eigenvectors of a nearby matrix.
 hipError_t launch_sym_eig(int batch, int ell, int r, const double* a, int64_t a_stride, double* w,
-                          int64_t w_stride, double* evals, int64_t ev_stride, hipStream_t st);
+                          int64_t w_stride, double* evals, int64_t ev_stride, hipStream_t st,
+                          const double* v_init = nullptr, int64_t v_stride = 0);
+
+// Up to kMaxDims independent eigenproblems of their own sizes in one launch.
+struct EigJob {
+  const double* a;
+  const double* v_init;  // optional starting basis
+  double* w;             // ell x r output
+  double* evals;         // optional
+  int ell, r;
+};
+struct EigJobs {
+  EigJob job[kMaxDims];
+};
+hipError_t launch_sym_eig_jobs(int njobs, const EigJob* jobs, hipStream_t st);
 
 }  // namespace krp

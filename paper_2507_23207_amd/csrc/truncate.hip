@@ -50,68 +50,109 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Cyclic Jacobi with the round-robin ("chess tournament") ordering: in every
-// round the np/2 disjoint pairs (p, q) are rotated at once.  A round reads
-// A_cur and writes A_next = J^T A_cur J block by block (every 2x2 block
-// {p1, q1} x {p2, q2} of A_next depends only on the same block of A_cur and
-// the two rotations).  Every wave computes the round's rotations itself (so
-// a round needs one workgroup barrier); pair indices are recomputed from the
-// round number; each thread owns one row pair k1 (and one pair of V's
-// columns) and loads every input of its tasks before it stores any result.
+// Cyclic Jacobi with a round-robin parallel ordering kept in "position
+// space": the np (even) indices occupy positions, every round rotates the
+// pairs of positions (2k, 2k+1) at once, and the rotated matrix is stored
+// with its positions moved by a fixed permutation sigma (the circle method
+// of round-robin scheduling: position 0 stays, the even positions advance,
+// the odd ones fall back), so that after np - 1 rounds every pair of
+// indices has met once.  Both A and the accumulated V = J_1 J_2 ... are
+// kept in position order (V's rows stay in index order), double-buffered in
+// LDS: a thread reads the 2x2 block {2k1, 2k1+1} x {2k2, 2k2+1} of A (two
+// aligned 16-byte loads, consecutive across lanes), forms J^T A J for it and
+// stores the four values at their permuted positions.  Every wave computes
+// the round's rotations itself, so a round costs one workgroup barrier.
 // Sweeps stop when the off-diagonal Frobenius norm is below 1e-13 of the
-// diagonal's.
-constexpr int kJBlocks = 4;  // block tasks per thread: ceil(32 / (256 / 32))
-constexpr int kJVtasks = 8;  // V tasks per thread: ceil(64 / (256 / 32))
+// diagonal's.  With v_init, the iteration starts from A = V0^T A_in V0,
+// V = V0 (a warm start from the eigenvectors of a nearby matrix).
+constexpr int kJTasks = 4;  // 2x2 tasks per thread: ceil(32 / (256 / 32))
+constexpr int kJPitch = kEigMax + 2;  // even, so 2-element pairs are 16-byte aligned
 
-// Pair k of round `round` in the round-robin schedule over np indices.
-__device__ __forceinline__ void jacobi_pair(int round, int k, int np, int& p, int& q) {
-  const int m = np - 1;
-  if (k == 0) {
-    p = m;
-    q = round;
-  } else {
-    p = round + k;
-    if (p >= m) p -= m;
-    q = round - k;
-    if (q < 0) q += m;
-  }
-  if (p > q) {
-    const int t = p;
-    p = q;
-    q = t;
-  }
+// 1 / sqrt(x) and 1 / x for positive normal x: hardware estimate plus two
+// Newton steps (relative error within a few ulp).
+__device__ __forceinline__ double rsqrt_nr(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  const double hx = 0.5 * x;
+  y = y * fma(-hx * y, y, 1.5);
+  y = y * fma(-hx * y, y, 1.5);
+  return y;
+}
+__device__ __forceinline__ double rcp_nr(double x) {
+  double y = __builtin_amdgcn_rcp(x);
+  y = fma(y, fma(-x, y, 1.0), y);
+  y = fma(y, fma(-x, y, 1.0), y);
+  return y;
+}
+
+__device__ __forceinline__ int jacobi_sigma(int x, int half) {
+  if (x == 0) return 0;
+  if (x & 1) return x == 1 ? (half > 1 ? 2 : 1) : x - 2;
+  return (x >> 1) == half - 1 ? x + 1 : x + 2;
 }
 
 __global__ __launch_bounds__(kEigThreads) void jacobi_eig_kernel(int ell, int r, const double* a_in,
-                                                                 int64_t a_stride, double* w,
+                                                                 int64_t a_stride, const double* v_init,
+                                                                 int64_t v_stride, double* w,
                                                                  int64_t w_stride, double* evals,
-                                                                 int64_t ev_stride) {
-  constexpr int P = kEigMax + 1;
+                                                                 int64_t ev_stride, int njobs,
+                                                                 EigJobs jobs) {
+  constexpr int P = kJPitch;
   constexpr int NW = kEigThreads / 64;
-  __shared__ double A[2][kEigMax * P];
-  __shared__ double V[kEigMax * P];
+  __shared__ __align__(16) double A[2][kEigMax * P];
+  __shared__ __align__(16) double VT[2][kEigMax * P];  // V^T: row = position, column = index
   __shared__ double2 rcs[NW][kEigMax / 2];
   __shared__ double red[2][NW];
   __shared__ int order_idx[kEigMax];
 
-  const int b = blockIdx.x;
+  int b = blockIdx.x;
+  if (njobs > 0) {  // independent problems of their own sizes
+    const EigJob& jb = jobs.job[b];
+    ell = jb.ell;
+    r = jb.r;
+    a_in = jb.a;
+    v_init = jb.v_init;
+    w = jb.w;
+    evals = jb.evals;
+    b = 0;
+  }
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int np = ell + (ell & 1);
   const int half = np / 2;
-  const int cpp = kEigThreads / half;  // thread columns per pass (>= 8)
+  const int cpp = kEigThreads / half;  // task rows per pass (>= 8)
   const bool active = tid < half * cpp;
-  const int k1 = tid % half, kb = tid / half;
+  const int k2 = tid % half, kb = tid / half;
   const double* ain = a_in + b * a_stride;
+  // A[0] <- input (padding index: -1 on the diagonal, decoupled, sorts last
+  // since the input is positive semi-definite); VT[0] <- identity or V0^T.
   for (int e = tid; e < np * np; e += kEigThreads) {
     const int i = e % np, j = e / np;
     double v = 0.0;
     if (i < ell && j < ell) v = ain[i + (int64_t)ell * j];
-    else if (i == j) v = -1.0;  // padding index: decoupled, sorts last (the input is PSD)
+    else if (i == j) v = -1.0;
+    double v0 = (i == j) ? 1.0 : 0.0;
+    if (v_init && i < ell && j < ell) v0 = v_init[b * v_stride + i + (int64_t)ell * j];
     A[0][i * P + j] = v;
-    V[i * P + j] = (i == j) ? 1.0 : 0.0;
+    VT[0][j * P + i] = v0;
   }
   __syncthreads();
   int cur = 0;
+  if (v_init) {
+    // T = A_in V0 into A[1], then A[0] = V0^T T
+    for (int e = tid; e < np * np; e += kEigThreads) {
+      const int i = e % np, j = e / np;
+      double s = 0.0;
+      for (int k = 0; k < np; ++k) s += A[0][i * P + k] * VT[0][j * P + k];
+      A[1][i * P + j] = s;
+    }
+    __syncthreads();
+    for (int e = tid; e < np * np; e += kEigThreads) {
+      const int i = e % np, j = e / np;
+      double s = 0.0;
+      for (int k = 0; k < np; ++k) s += VT[0][i * P + k] * A[1][k * P + j];
+      A[0][i * P + j] = s;
+    }
+    __syncthreads();
+  }
   for (int sweep = 0; sweep < 60; ++sweep) {
     double off = 0.0, dia = 0.0;
     for (int e = tid; e < np * np; e += kEigThreads) {
@@ -137,76 +178,77 @@ __global__ __launch_bounds__(kEigThreads) void jacobi_eig_kernel(int ell, int r,
     for (int round = 0; round < np - 1; ++round) {
       const double* Ac = A[cur];
       double* An = A[cur ^ 1];
-      if (lane < half) {
-        int p, q;
-        jacobi_pair(round, lane, np, p, q);
-        const double apq = Ac[p * P + q];
-        const double app = Ac[p * P + p], aqq = Ac[q * P + q];
-        double c = 1.0, s = 0.0;
-        if (apq != 0.0) {
-          const double theta = (aqq - app) / (2.0 * apq);
-          const double t = (theta >= 0.0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
-          c = 1.0 / sqrt(t * t + 1.0);
-          s = t * c;
+      const double* Vc = VT[cur];
+      double* Vn = VT[cur ^ 1];
+      // loads of this thread's tasks first: they do not depend on the rotations
+      double2 ra[kJTasks], rb[kJTasks], va[kJTasks], vb[kJTasks];
+      if (active) {
+#pragma unroll
+        for (int u = 0; u < kJTasks; ++u) {
+          const int k1 = kb + u * cpp;
+          if (k1 < half) {
+            ra[u] = *reinterpret_cast<const double2*>(&Ac[(2 * k1) * P + 2 * k2]);
+            rb[u] = *reinterpret_cast<const double2*>(&Ac[(2 * k1 + 1) * P + 2 * k2]);
+            va[u] = *reinterpret_cast<const double2*>(&Vc[(2 * k1) * P + 2 * k2]);
+            vb[u] = *reinterpret_cast<const double2*>(&Vc[(2 * k1 + 1) * P + 2 * k2]);
+          }
         }
-        rcs[wave][lane] = make_double2(c, s);
+      }
+      if (lane < half) {
+        // rotation of positions (2k, 2k+1) zeroing their off-diagonal entry:
+        // t = tan(phi) = sign(d) 2 apq / (|d| + sqrt(d^2 + 4 apq^2)), d = aqq - app
+        // The reciprocal square roots and the reciprocal use the hardware
+        // estimates refined by two Newton steps each: t only has to be close
+        // to the exact angle (c and s stay exactly normalised by c = 1 /
+        // sqrt(1 + t^2), s = t c), and this keeps the dependent chain short.
+        const int p = 2 * lane;
+        const double app = Ac[p * P + p], apq = Ac[p * P + p + 1], aqq = Ac[(p + 1) * P + p + 1];
+        const double d = aqq - app;
+        double t = 0.0;
+        const double num = 2.0 * apq;
+        const double x = fma(d, d, num * num);
+        if (apq != 0.0 && x >= 0x1.0p-1000) {  // (entries below ~1e-150 count as zero)
+          const double hyp = x * rsqrt_nr(x);
+          t = num * rcp_nr(fabs(d) + hyp);
+          if (d < 0.0) t = -t;
+        }
+        const double c = rsqrt_nr(fma(t, t, 1.0));
+        rcs[wave][lane] = make_double2(c, t * c);
       }
       wave_sync();
       if (active) {
-        int p1, q1;
-        jacobi_pair(round, k1, np, p1, q1);
-        const double2 r1 = rcs[wave][k1];
-        int p2[kJBlocks], q2[kJBlocks], pv[kJVtasks];
-        double2 r2[kJBlocks];
-        double bb[kJBlocks][4], v0[kJVtasks], v1[kJVtasks];
-        // loads
+        const double2 r2 = rcs[wave][k2];
+        const double c2 = r2.x, s2 = r2.y;
+        const int cp = jacobi_sigma(2 * k2, half), cq = jacobi_sigma(2 * k2 + 1, half);
 #pragma unroll
-        for (int u = 0; u < kJBlocks; ++u) {
-          const int k2 = kb + u * cpp;
-          if (k2 < half) {
-            jacobi_pair(round, k2, np, p2[u], q2[u]);
-            r2[u] = rcs[wave][k2];
-            bb[u][0] = Ac[p1 * P + p2[u]];
-            bb[u][1] = Ac[p1 * P + q2[u]];
-            bb[u][2] = Ac[q1 * P + p2[u]];
-            bb[u][3] = Ac[q1 * P + q2[u]];
-          }
-        }
-#pragma unroll
-        for (int u = 0; u < kJVtasks; ++u) {
-          const int i = kb + u * cpp;
-          if (i < np) {
-            pv[u] = i * P;
-            v0[u] = V[pv[u] + p1];
-            v1[u] = V[pv[u] + q1];
-          }
-        }
-        // rotations and stores
-#pragma unroll
-        for (int u = 0; u < kJBlocks; ++u) {
-          const int k2 = kb + u * cpp;
-          if (k2 < half) {
-            const double c2 = r2[u].x, s2 = r2[u].y, c1 = r1.x, s1 = r1.y;
-            const double t00 = c2 * bb[u][0] - s2 * bb[u][1], t01 = s2 * bb[u][0] + c2 * bb[u][1];
-            const double t10 = c2 * bb[u][2] - s2 * bb[u][3], t11 = s2 * bb[u][2] + c2 * bb[u][3];
+        for (int u = 0; u < kJTasks; ++u) {
+          const int k1 = kb + u * cpp;
+          if (k1 < half) {
+            const double2 r1 = rcs[wave][k1];
+            const double c1 = r1.x, s1 = r1.y;
+            // columns: (A J)[:, p] = c A[:, p] - s A[:, q], (A J)[:, q] = s A[:, p] + c A[:, q]
+            const double t00 = c2 * ra[u].x - s2 * ra[u].y, t01 = s2 * ra[u].x + c2 * ra[u].y;
+            const double t10 = c2 * rb[u].x - s2 * rb[u].y, t11 = s2 * rb[u].x + c2 * rb[u].y;
+            // rows: J^T (A J)
             double n00 = c1 * t00 - s1 * t10, n01 = c1 * t01 - s1 * t11;
             double n10 = s1 * t00 + c1 * t10, n11 = s1 * t01 + c1 * t11;
-            if (k2 == k1) {
+            if (k1 == k2) {
               n01 = 0.0;
               n10 = 0.0;
             }
-            An[p1 * P + p2[u]] = n00;
-            An[p1 * P + q2[u]] = n01;
-            An[q1 * P + p2[u]] = n10;
-            An[q1 * P + q2[u]] = n11;
-          }
-        }
-#pragma unroll
-        for (int u = 0; u < kJVtasks; ++u) {
-          const int i = kb + u * cpp;
-          if (i < np) {
-            V[pv[u] + p1] = r1.x * v0[u] - r1.y * v1[u];
-            V[pv[u] + q1] = r1.y * v0[u] + r1.x * v1[u];
+            const int rp = jacobi_sigma(2 * k1, half), rq = jacobi_sigma(2 * k1 + 1, half);
+            An[rp * P + cp] = n00;
+            An[rp * P + cq] = n01;
+            An[rq * P + cp] = n10;
+            An[rq * P + cq] = n11;
+            // V^T <- J^T V^T on rows (2 k1, 2 k1 + 1), columns 2 k2 and 2 k2 + 1
+            double2 w0, w1;
+            w0.x = c1 * va[u].x - s1 * vb[u].x;
+            w0.y = c1 * va[u].y - s1 * vb[u].y;
+            w1.x = s1 * va[u].x + c1 * vb[u].x;
+            w1.y = s1 * va[u].y + c1 * vb[u].y;
+            *reinterpret_cast<double2*>(&Vn[rp * P + 2 * k2]) = w0;
+            *reinterpret_cast<double2*>(&Vn[rq * P + 2 * k2]) = w1;
           }
         }
       }
@@ -214,7 +256,7 @@ __global__ __launch_bounds__(kEigThreads) void jacobi_eig_kernel(int ell, int r,
       cur ^= 1;
     }
   }
-  // descending eigenvalues by ranking (ties keep the lower index first)
+  // descending eigenvalues by ranking (ties keep the lower position first)
   if (tid < np) order_idx[tid] = tid;
   __syncthreads();
   if (tid < np) {
@@ -230,17 +272,18 @@ __global__ __launch_bounds__(kEigThreads) void jacobi_eig_kernel(int ell, int r,
   double* wout = w + b * w_stride;
   for (int j = tid; j < r; j += kEigThreads) {
     const int c = order_idx[j];
+    const double* vc = &VT[cur][c * P];
     int imax = 0;
     double vmax = -1.0;
     for (int i = 0; i < ell; ++i) {
-      const double v = fabs(V[i * P + c]);
+      const double v = fabs(vc[i]);
       if (v > vmax) {
         vmax = v;
         imax = i;
       }
     }
-    const double sgn = V[imax * P + c] < 0.0 ? -1.0 : 1.0;
-    for (int i = 0; i < ell; ++i) wout[i + (int64_t)ell * j] = sgn * V[i * P + c];
+    const double sgn = vc[imax] < 0.0 ? -1.0 : 1.0;
+    for (int i = 0; i < ell; ++i) wout[i + (int64_t)ell * j] = sgn * vc[i];
     if (evals) evals[b * ev_stride + j] = A[cur][c * (P + 1)];
   }
 }
@@ -285,7 +328,8 @@ TruncPlan plan_truncate(int d, const int* ell, const int* rank, const int64_t* d
   };
   p.off_g[0] = take(elems * sizeof(double));
   p.off_g[1] = take(elems * sizeof(double));
-  p.off_gram = take((size_t)kEigMax * kEigMax * sizeof(double));
+  for (int k = 0; k < d; ++k) p.off_gram[k] = take((size_t)ell[k] * ell[k] * sizeof(double));
+  for (int k = 0; k < d; ++k) p.off_v0[k] = take((size_t)ell[k] * ell[k] * sizeof(double));
   for (int k = 0; k < d; ++k) p.off_w[k] = take((size_t)ell[k] * rank[k] * sizeof(double));
   for (int k = 0; k < d; ++k) p.off_qt[k] = take((size_t)dims[k] * rank[k] * sizeof(double));
   p.ws_bytes = off;
@@ -297,11 +341,25 @@ double* truncated_q64(const TruncPlan& p, char* ws, int k) {
 }
 
 hipError_t launch_sym_eig(int batch, int ell, int r, const double* a, int64_t a_stride, double* w,
-                          int64_t w_stride, double* evals, int64_t ev_stride, hipStream_t st) {
+                          int64_t w_stride, double* evals, int64_t ev_stride, hipStream_t st,
+                          const double* v_init, int64_t v_stride) {
   if (ell < 1 || ell > kEigMax || r < 1 || r > ell) return hipErrorInvalidValue;
   if (batch == 0) return hipSuccess;
-  hipLaunchKernelGGL(jacobi_eig_kernel, dim3(batch), dim3(kEigThreads), 0, st, ell, r, a, a_stride, w,
-                     w_stride, evals, ev_stride);
+  hipLaunchKernelGGL(jacobi_eig_kernel, dim3(batch), dim3(kEigThreads), 0, st, ell, r, a, a_stride,
+                     v_init, v_stride, w, w_stride, evals, ev_stride, 0, EigJobs{});
+  return hipGetLastError();
+}
+
+hipError_t launch_sym_eig_jobs(int njobs, const EigJob* jobs, hipStream_t st) {
+  if (njobs < 1 || njobs > kMaxDims) return hipErrorInvalidValue;
+  EigJobs t{};
+  for (int k = 0; k < njobs; ++k) {
+    const EigJob& j = jobs[k];
+    if (j.ell < 1 || j.ell > kEigMax || j.r < 1 || j.r > j.ell) return hipErrorInvalidValue;
+    t.job[k] = j;
+  }
+  hipLaunchKernelGGL(jacobi_eig_kernel, dim3(njobs), dim3(kEigThreads), 0, st, 0, 0, nullptr, 0,
+                     nullptr, 0, nullptr, 0, nullptr, 0, njobs, t);
   return hipGetLastError();
 }
 
@@ -318,19 +376,44 @@ hipError_t launch_truncate(const TruncPlan& p, const void* core, int core_double
   double* g[2] = {reinterpret_cast<double*>(ws + p.off_g[0]), reinterpret_cast<double*>(ws + p.off_g[1])};
   hipError_t e = launch_cast(core, core_double, g[0], 1, elems, st);
   if (e != hipSuccess) return e;
-  double* gram = reinterpret_cast<double*>(ws + p.off_gram);
-  for (int s = 0; s < d; ++s) {
-    const int i = p.order[s];
+  auto gram_of = [&](const double* src, int i, double* gram) {
     int64_t P = 1, Q = 1;
     for (int k = 0; k < i; ++k) P *= cur[k];
     for (int k = i + 1; k < d; ++k) Q *= cur[k];
     const int l = (int)cur[i];
-    const int npairs = l * (l + 1) / 2;
-    hipLaunchKernelGGL(mode_gram_kernel, dim3(npairs), dim3(kGramThreads), 0, st, g[s & 1], P, l, Q, gram);
-    e = hipGetLastError();
+    hipLaunchKernelGGL(mode_gram_kernel, dim3(l * (l + 1) / 2), dim3(kGramThreads), 0, st, src, P, l, Q,
+                       gram);
+    return hipGetLastError();
+  };
+  // The Gram matrices of all modes of the ell-core, and their complete
+  // eigenbases in one launch (the modes are independent problems).  The first
+  // mode of the order uses them as they are; every later mode's Gram matrix
+  // (of the partially truncated core) differs from its ell-core counterpart
+  // only by the discarded components, so its Jacobi iteration starts from
+  // that basis and needs few sweeps.
+  EigJob jobs[kMaxDims];
+  for (int i = 0; i < d; ++i) {
+    double* gram = reinterpret_cast<double*>(ws + p.off_gram[i]);
+    e = gram_of(g[0], i, gram);
     if (e != hipSuccess) return e;
+    jobs[i] = EigJob{gram, nullptr, reinterpret_cast<double*>(ws + p.off_v0[i]), nullptr, p.ell[i], p.ell[i]};
+  }
+  e = launch_sym_eig_jobs(d, jobs, st);
+  if (e != hipSuccess) return e;
+  for (int s = 0; s < d; ++s) {
+    const int i = p.order[s];
+    const int l = (int)cur[i];
     double* wi = reinterpret_cast<double*>(ws + p.off_w[i]);
-    e = launch_sym_eig(1, l, p.rank[i], gram, 0, wi, 0, nullptr, 0, st);
+    const double* v0 = reinterpret_cast<const double*>(ws + p.off_v0[i]);
+    if (s == 0) {
+      // leading r columns of the (sorted, sign-normalised) eigenbasis
+      e = launch_cast(v0, 1, wi, 1, (int64_t)l * p.rank[i], st);
+    } else {
+      double* gram = reinterpret_cast<double*>(ws + p.off_gram[i]);
+      e = gram_of(g[s & 1], i, gram);
+      if (e != hipSuccess) return e;
+      e = launch_sym_eig(1, l, p.rank[i], gram, 0, wi, 0, nullptr, 0, st, v0, 0);
+    }
     if (e != hipSuccess) return e;
     TtmProblem tp;
     tp.g = g[s & 1];
