@@ -40,7 +40,8 @@ struct SketchPlan {
   int o_fid[kMaxDims];
   int64_t o_total, o_per_wg;
   int o_ranges, f_blocks, row_blocks, col_chunks;
-  int mt, nt, wm, wo, kvec;
+  int mt, nt, wm, wo, kvec, xpose;
+  size_t stage_bytes;     // per-wave transposition staging (mode 0), all waves
   int cpad, nparts;
   int lds_rows;           // factor-table rows the LDS allocation holds
   size_t lds_bytes;

@@ -25,6 +25,21 @@ struct u64x4 {
   uint64_t v0, v1, v2, v3;
 };
 
+// Full 64 x 64 -> 128-bit product by a constant from four 32 x 32 -> 64
+// partial products (the low and high halves share them).
+template <uint64_t K>
+__device__ __forceinline__ void mul128(uint64_t x, uint64_t& lo, uint64_t& hi) {
+  constexpr uint32_t kl = (uint32_t)K, kh = (uint32_t)(K >> 32);
+  const uint32_t xl = (uint32_t)x, xh = (uint32_t)(x >> 32);
+  const uint64_t p00 = (uint64_t)xl * kl;
+  const uint64_t p01 = (uint64_t)xl * kh;
+  const uint64_t p10 = (uint64_t)xh * kl;
+  const uint64_t p11 = (uint64_t)xh * kh;
+  const uint64_t mid = (p00 >> 32) + (uint32_t)p01 + (uint32_t)p10;
+  lo = (mid << 32) | (uint32_t)p00;
+  hi = p11 + (p01 >> 32) + (p10 >> 32) + (mid >> 32);
+}
+
 __device__ __forceinline__ u64x4 philox4x64_10(u64x4 c, uint64_t k0, uint64_t k1) {
   constexpr uint64_t kMul0 = 0xD2E7470EE14C6C93ull;
   constexpr uint64_t kMul1 = 0xCA5A826395121157ull;
@@ -32,8 +47,9 @@ __device__ __forceinline__ u64x4 philox4x64_10(u64x4 c, uint64_t k0, uint64_t k1
   constexpr uint64_t kWeyl1 = 0xBB67AE8584CAA73Bull;
 #pragma unroll
   for (int r = 0; r < 10; ++r) {
-    const uint64_t lo0 = kMul0 * c.v0, hi0 = __umul64hi(kMul0, c.v0);
-    const uint64_t lo1 = kMul1 * c.v2, hi1 = __umul64hi(kMul1, c.v2);
+    uint64_t lo0, hi0, lo1, hi1;
+    mul128<kMul0>(c.v0, lo0, hi0);
+    mul128<kMul1>(c.v2, lo1, hi1);
     u64x4 n;
     n.v0 = hi1 ^ c.v1 ^ k0;
     n.v1 = lo1;
@@ -117,25 +133,19 @@ __device__ __forceinline__ double cos_two_pi(uint64_t k2) {
   const double f = (double)rem * 0x1.0p-53;
   const double th = kTwoPi * f;
   const double z = th * th;
-  double c = kCos[10];
+  // One Horner chain per entry: the cosine sum (quadrants 0, 2) or the sine
+  // sum (1, 3).  The sine chain starts from 0, whose first step gives
+  // kSin[9] exactly, so both produce the same operations as separate sums.
+  const bool odd = (q & 1) != 0;
+  double p = odd ? 0.0 : kCos[10];
 #pragma unroll
   for (int j = 9; j >= 0; --j) {
-    c = c * z;
-    c = c + kCos[j];
+    p = p * z;
+    p = p + (odd ? kSin[j] : kCos[j]);
   }
-  double sp = kSin[9];
-#pragma unroll
-  for (int j = 8; j >= 0; --j) {
-    sp = sp * z;
-    sp = sp + kSin[j];
-  }
-  const double s = th * sp;
-  switch ((int)(q & 3)) {
-    case 0: return c;
-    case 1: return -s;
-    case 2: return -c;
-    default: return s;
-  }
+  const double v = odd ? th * p : p;
+  // quadrant 0: cos, 1: -sin, 2: -cos, 3: sin
+  return ((q + 1) & 2) ? -v : v;
 }
 
 __device__ __forceinline__ double gauss_from_words(uint64_t w0, uint64_t w1) {

@@ -30,15 +30,25 @@ struct SketchArgs {
   int n_out;
   int64_t o_total, o_per_wg;
   int f_blocks, ell, nparts, wm, wo, rows_per_wg, fid_f, lds_rows;
+  int64_t stage_off;  // byte offset of the per-wave staging regions (kLoadXpose)
   uint64_t seed, w2_base;
 };
 
+// Load modes of the X slab:
+//   kLoadScalar  one element per lane and slot (any strides);
+//   kLoadVecF    16-byte loads along the 32-wide f block (f contiguous);
+//   kLoadXpose   16-byte loads along the rows (mode 0, rows contiguous), each
+//                wave transposing its 16 MT x 32 slab through a private LDS
+//                region into the fragment layout.
+enum LoadMode : int { kLoadScalar = 0, kLoadVecF = 1, kLoadXpose = 2 };
+
 // Reduction slot -> k offset inside the 32-wide block.  With vector loads
-// (the block is contiguous in memory) lane group g reads 16-byte pieces so
-// that the four groups of a row cover 64 contiguous bytes per instruction.
-template <typename Tin, bool KVEC>
+// along f (the block is contiguous in memory) lane group g reads 16-byte
+// pieces so that the four groups of a row cover 64 contiguous bytes per
+// instruction.
+template <typename Tin, int LM>
 __device__ __forceinline__ int kmap(int g, int j) {
-  if constexpr (KVEC) {
+  if constexpr (LM == kLoadVecF) {
     constexpr int V = 16 / sizeof(Tin);
     return V * g + 4 * V * (j / V) + (j % V);
   } else {
@@ -46,7 +56,15 @@ __device__ __forceinline__ int kmap(int g, int j) {
   }
 }
 
-template <typename Tin, int P, bool KVEC, int MT, int NT>
+// Pitch (elements) of a wave's transposed staging region [k][row]: 16 MT rows
+// plus 2, so that the fragment reads (16 consecutive rows at four k 8 apart)
+// fall on distinct banks and the 8-byte writes stay aligned.
+template <int MT>
+constexpr int xpose_pitch() {
+  return 16 * MT + 2;
+}
+
+template <typename Tin, int P, int LM, int MT, int NT>
 __global__ __launch_bounds__(512) void sketch_kernel(SketchArgs a) {
   using Pol = Policy<P>;
   using T = typename Pol::T;
@@ -90,6 +108,7 @@ __global__ __launch_bounds__(512) void sketch_kernel(SketchArgs a) {
   AccT* part = reinterpret_cast<AccT*>(a.partial) +
                ((int64_t)blockIdx.z * a.nparts + (int64_t)kg * a.wo + w_o) * a.n_rows * CP;
   const int n = lane & 15, g = lane >> 4;
+  Tin* stage = reinterpret_cast<Tin*>(smem_raw + a.stage_off) + (int64_t)wave * 32 * xpose_pitch<MT>();
   // The host sized the LDS for lds_rows table rows.  A plan that undercounts
   // would be a planner bug: the workgroup then poisons its partial sums with
   // NaN (reported as non-finite by the QR) instead of overrunning the LDS.
@@ -107,27 +126,6 @@ __global__ __launch_bounds__(512) void sketch_kernel(SketchArgs a) {
     return;
   }
 
-  // Draw the factor rows (fp64 Gaussians rounded to the working precision).
-  for (int e = threadIdx.x; e < rows_total * CP; e += blockDim.x) {
-    const int r = e / CP, c = e - (e / CP) * CP;
-    const int gc = col0 + c;
-    T v = (T)0;
-    if (gc < a.ell) {
-      if (r < 32) {
-        const int64_t row = f0 + r;
-        if (row < a.n_f) v = factor_value<P>(gauss_entry(a.seed, a.w2_base | (uint64_t)a.fid_f, 0, row, gc));
-      } else {
-        int k = 0;
-#pragma unroll
-        for (int kk = 1; kk < kMaxDims; ++kk)
-          if (kk < a.n_out && r >= toff[kk]) k = kk;
-        const int64_t row = (lo[k] + (r - toff[k])) % a.o_size[k];
-        v = factor_value<P>(gauss_entry(a.seed, a.w2_base | (uint64_t)a.o_fid[k], 0, row, gc));
-      }
-    }
-    tab[e] = v;
-  }
-  __syncthreads();
 
   typename Pol::Acc acc[MT][NT];
 #pragma unroll
@@ -177,12 +175,46 @@ __global__ __launch_bounds__(512) void sketch_kernel(SketchArgs a) {
   };
   // A fragments of outer step z (raw input values, converted at use).
   auto load_a = [&](Tin (&buf)[MT][8], const Odo& z) {
+    if constexpr (LM == kLoadXpose) {
+      // rows (contiguous) in 16-byte pieces: lane = (row group rg, k offset kq)
+      constexpr int V = 16 / sizeof(Tin);
+      constexpr int RG = 16 * MT / V;       // row groups of the wave's rows
+      constexpr int KQ = 64 / RG;           // k values per instruction
+      constexpr int NL = 32 / KQ;           // loads per lane
+      const int rg = lane % RG, kq = lane / RG;
+      const int64_t row = a0 + (int64_t)V * rg;
+      const bool rv = row < a.n_rows;
+#pragma unroll
+      for (int h = 0; h < NL; ++h) {
+        const int64_t kk = f0 + kq + KQ * h;
+        Tin q[V];
+#pragma unroll
+        for (int v = 0; v < V; ++v) q[v] = (Tin)0;
+        if (rv && kk < a.n_f) {
+          const Tin* src = X + z.off + row + kk * a.s_f;
+          if constexpr (sizeof(Tin) == 4) {
+            const float4 t = *reinterpret_cast<const float4*>(src);
+            q[0] = t.x;
+            q[1] = t.y;
+            q[2] = t.z;
+            q[3] = t.w;
+          } else {
+            const double2 t = *reinterpret_cast<const double2*>(src);
+            q[0] = t.x;
+            q[1] = t.y;
+          }
+        }
+#pragma unroll
+        for (int v = 0; v < V; ++v) buf[(h * V + v) / 8][(h * V + v) % 8] = q[v];
+      }
+      return;
+    }
 #pragma unroll
     for (int m = 0; m < MT; ++m) {
       const int64_t row = a0 + 16 * m + n;
       const bool rv = row < a.n_rows;
       const int64_t base = z.off + row * a.s_row + f0 * a.s_f;
-      if constexpr (KVEC) {
+      if constexpr (LM == kLoadVecF) {
         if constexpr (sizeof(Tin) == 4) {
 #pragma unroll
           for (int h = 0; h < 2; ++h) {
@@ -233,14 +265,54 @@ __global__ __launch_bounds__(512) void sketch_kernel(SketchArgs a) {
     for (int t = 0; t < NT; ++t) {
       T v[8];
 #pragma unroll
-      for (int j = 0; j < 8; ++j) v[j] = tab[kmap<Tin, KVEC>(g, j) * CP + 16 * t + n] * w[t];
+      for (int j = 0; j < 8; ++j) v[j] = tab[kmap<Tin, LM>(g, j) * CP + 16 * t + n] * w[t];
       bf[t] = Pol::make(v);
+    }
+    Tin xa[MT][8];
+    if constexpr (LM == kLoadXpose) {
+      // through the wave's staging region: [k][row], pitch xpose_pitch<MT>()
+      constexpr int V = 16 / sizeof(Tin);
+      constexpr int RG = 16 * MT / V;
+      constexpr int KQ = 64 / RG;
+      constexpr int NL = 32 / KQ;
+      constexpr int PT = xpose_pitch<MT>();
+      const int rg = lane % RG, kq = lane / RG;
+#pragma unroll
+      for (int h = 0; h < NL; ++h) {
+        Tin* d = stage + (kq + KQ * h) * PT + V * rg;
+#pragma unroll
+        for (int v = 0; v < V; v += 2) {
+          if constexpr (sizeof(Tin) == 4) {
+            *reinterpret_cast<float2*>(d + v) =
+                make_float2(buf[(h * V + v) / 8][(h * V + v) % 8], buf[(h * V + v + 1) / 8][(h * V + v + 1) % 8]);
+          } else {
+            *reinterpret_cast<double2*>(d + v) =
+                make_double2(buf[(h * V + v) / 8][(h * V + v) % 8], buf[(h * V + v + 1) / 8][(h * V + v + 1) % 8]);
+          }
+        }
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+      for (int m = 0; m < MT; ++m)
+#pragma unroll
+        for (int j = 0; j < 8; ++j) xa[m][j] = stage[(8 * g + j) * PT + 16 * m + n];
+      // the next step's stores must not overtake these reads
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    } else {
+#pragma unroll
+      for (int m = 0; m < MT; ++m)
+#pragma unroll
+        for (int j = 0; j < 8; ++j) xa[m][j] = buf[m][j];
     }
 #pragma unroll
     for (int m = 0; m < MT; ++m) {
       T v[8];
 #pragma unroll
-      for (int j = 0; j < 8; ++j) v[j] = (T)buf[m][j];
+      for (int j = 0; j < 8; ++j) v[j] = (T)xa[m][j];
       const typename Pol::Frag af = Pol::make(v);
 #pragma unroll
       for (int t = 0; t < NT; ++t) Pol::mma(acc[m][t], af, bf[t]);
@@ -252,6 +324,28 @@ __global__ __launch_bounds__(512) void sketch_kernel(SketchArgs a) {
   Tin bufA[MT][8], bufB[MT][8];
   Odo cur = odo_init(o_begin + w_o);
   if (cur.o < o_end) load_a(bufA, cur);
+  // The factor table is drawn while the first slab loads are in flight.
+  // Draw the factor rows (fp64 Gaussians rounded to the working precision).
+  for (int e = threadIdx.x; e < rows_total * CP; e += blockDim.x) {
+    const int r = e / CP, c = e - (e / CP) * CP;
+    const int gc = col0 + c;
+    T v = (T)0;
+    if (gc < a.ell) {
+      if (r < 32) {
+        const int64_t row = f0 + r;
+        if (row < a.n_f) v = factor_value<P>(gauss_entry(a.seed, a.w2_base | (uint64_t)a.fid_f, 0, row, gc));
+      } else {
+        int k = 0;
+#pragma unroll
+        for (int kk = 1; kk < kMaxDims; ++kk)
+          if (kk < a.n_out && r >= toff[kk]) k = kk;
+        const int64_t row = (lo[k] + (r - toff[k])) % a.o_size[k];
+        v = factor_value<P>(gauss_entry(a.seed, a.w2_base | (uint64_t)a.o_fid[k], 0, row, gc));
+      }
+    }
+    tab[e] = v;
+  }
+  __syncthreads();
   while (cur.o < o_end) {
     Odo nxt = cur;
     odo_step(nxt, a.wo);
@@ -357,9 +451,9 @@ __global__ void gaussian_kernel(uint64_t seed, uint64_t w2, uint64_t instance, i
   }
 }
 
-template <typename Tin, int P, bool KVEC, int MT, int NT>
+template <typename Tin, int P, int LM, int MT, int NT>
 hipError_t launch_inst(const SketchArgs& args, dim3 grid, int threads, size_t lds, hipStream_t st) {
-  auto kern = sketch_kernel<Tin, P, KVEC, MT, NT>;
+  auto kern = sketch_kernel<Tin, P, LM, MT, NT>;
   if (lds > 65536) {
     hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
@@ -368,31 +462,32 @@ hipError_t launch_inst(const SketchArgs& args, dim3 grid, int threads, size_t ld
   return hipGetLastError();
 }
 
-template <typename Tin, int P, bool KVEC, int MT>
+template <typename Tin, int P, int LM, int MT>
 hipError_t dispatch_nt(int nt, const SketchArgs& args, dim3 grid, int threads, size_t lds, hipStream_t st) {
   switch (nt) {
-    case 1: return launch_inst<Tin, P, KVEC, MT, 1>(args, grid, threads, lds, st);
-    case 2: return launch_inst<Tin, P, KVEC, MT, 2>(args, grid, threads, lds, st);
-    case 3: return launch_inst<Tin, P, KVEC, MT, 3>(args, grid, threads, lds, st);
-    default: return launch_inst<Tin, P, KVEC, MT, 4>(args, grid, threads, lds, st);
+    case 1: return launch_inst<Tin, P, LM, MT, 1>(args, grid, threads, lds, st);
+    case 2: return launch_inst<Tin, P, LM, MT, 2>(args, grid, threads, lds, st);
+    case 3: return launch_inst<Tin, P, LM, MT, 3>(args, grid, threads, lds, st);
+    default: return launch_inst<Tin, P, LM, MT, 4>(args, grid, threads, lds, st);
   }
 }
 
-template <typename Tin, int P, bool KVEC>
+template <typename Tin, int P, int LM>
 hipError_t dispatch_mt(int mt, int nt, const SketchArgs& args, dim3 grid, int threads, size_t lds,
                        hipStream_t st) {
   switch (mt) {
-    case 1: return dispatch_nt<Tin, P, KVEC, 1>(nt, args, grid, threads, lds, st);
-    case 2: return dispatch_nt<Tin, P, KVEC, 2>(nt, args, grid, threads, lds, st);
-    default: return dispatch_nt<Tin, P, KVEC, 4>(nt, args, grid, threads, lds, st);
+    case 1: return dispatch_nt<Tin, P, LM, 1>(nt, args, grid, threads, lds, st);
+    case 2: return dispatch_nt<Tin, P, LM, 2>(nt, args, grid, threads, lds, st);
+    default: return dispatch_nt<Tin, P, LM, 4>(nt, args, grid, threads, lds, st);
   }
 }
 
 template <typename Tin, int P>
-hipError_t dispatch_kvec(int kvec, int mt, int nt, const SketchArgs& args, dim3 grid, int threads,
-                         size_t lds, hipStream_t st) {
-  if (kvec) return dispatch_mt<Tin, P, true>(mt, nt, args, grid, threads, lds, st);
-  return dispatch_mt<Tin, P, false>(mt, nt, args, grid, threads, lds, st);
+hipError_t dispatch_lm(int lm, int mt, int nt, const SketchArgs& args, dim3 grid, int threads,
+                       size_t lds, hipStream_t st) {
+  if (lm == kLoadVecF) return dispatch_mt<Tin, P, kLoadVecF>(mt, nt, args, grid, threads, lds, st);
+  if (lm == kLoadXpose) return dispatch_mt<Tin, P, kLoadXpose>(mt, nt, args, grid, threads, lds, st);
+  return dispatch_mt<Tin, P, kLoadScalar>(mt, nt, args, grid, threads, lds, st);
 }
 
 }  // namespace
@@ -429,9 +524,14 @@ SketchPlan plan_sketch(const SketchProblem& pb, const SketchTile& tile) {
   int mt = tile.mt;
   if (mt != 1 && mt != 2) mt = 4;
   while (mt > 1 && 16 * (mt / 2) >= p.n_rows) mt /= 2;
-  // Scalar (strided) loads need one 64-bit address per element: keep the
-  // register budget within two waves per SIMD by halving the row tiles.
-  if (i == 0 && mt > 2) mt = 2;
+  // Mode 0 reads rows along the contiguous index.  Scalar (strided) loads
+  // need one 64-bit address per element: keep the register budget within two
+  // waves per SIMD by halving the row tiles.  The staged 16-byte path
+  // (fp32 storage, 16-byte aligned data, n_0 a multiple of 4) keeps 64 rows.
+  const int64_t vlen = 16 / (pb.x_is_double ? 8 : 4);
+  const bool x_aligned = (reinterpret_cast<uintptr_t>(pb.x) & 15) == 0;
+  p.xpose = (i == 0) && pb.d >= 2 && (p.n_rows % vlen == 0);
+  if (i == 0 && mt > 2 && !(p.xpose && x_aligned && !pb.x_is_double)) mt = 2;
   if (fp64 && mt > 2 && p.nt >= 3) mt = 2;  // register budget of fp64 fragments
   p.mt = mt;
   const int64_t wave_rows = 16 * mt;
@@ -442,7 +542,7 @@ SketchPlan plan_sketch(const SketchProblem& pb, const SketchTile& tile) {
   while (p.wm * wo > 8) --wo;
   p.wo = std::max(1, wo);
   p.f_blocks = (int)((p.n_f + 31) / 32);
-  p.kvec = (i != 0) && (p.n_f % (int64_t)(16 / (pb.x_is_double ? 8 : 4)) == 0);
+  p.kvec = (i != 0) && (p.n_f % vlen == 0);
 
   int64_t o_per = tile.o_per_wg;
   if (o_per <= 0) {
@@ -465,6 +565,7 @@ SketchPlan plan_sketch(const SketchProblem& pb, const SketchTile& tile) {
     o_per = (o_per + 1) / 2;
   }
   p.o_per_wg = o_per;
+  p.stage_bytes = (size_t)8 * 32 * (16 * p.mt + 2) * (pb.x_is_double ? 8 : 4);  // 8 waves (upper bound)
   p.o_ranges = (int)((p.o_total + o_per - 1) / o_per);
   p.nparts = p.f_blocks * p.o_ranges * p.wo;
   p.partial_bytes = (size_t)p.col_chunks * p.nparts * p.n_rows * p.cpad * tsz;
@@ -503,19 +604,25 @@ hipError_t launch_sketch(const SketchProblem& pb, const SketchPlan& p, void* par
   a.w2_base = counter_word2(pb.draw, pb.sketch_id, 0);
 
   // Vector loads need 16-byte aligned rows; misaligned views take the scalar path.
-  const int kvec = p.kvec && ((reinterpret_cast<uintptr_t>(pb.x) & 15) == 0);
+  const bool aligned = (reinterpret_cast<uintptr_t>(pb.x) & 15) == 0;
+  int lm = kLoadScalar;
+  if (aligned && p.kvec) lm = kLoadVecF;
+  if (aligned && p.xpose) lm = kLoadXpose;
+  size_t lds = p.lds_bytes;
+  a.stage_off = (int64_t)((lds + 15) / 16 * 16);
+  if (lm == kLoadXpose) lds = (size_t)a.stage_off + p.stage_bytes;
   const dim3 grid((unsigned)(p.f_blocks * p.o_ranges), (unsigned)p.row_blocks, (unsigned)p.col_chunks);
   const int threads = 64 * p.wm * p.wo;
   hipError_t e;
   if (pb.x_is_double) {
     if (pb.prec != kFP64) return hipErrorInvalidValue;
-    e = dispatch_kvec<double, kFP64>(kvec, p.mt, p.nt, a, grid, threads, p.lds_bytes, st);
+    e = dispatch_lm<double, kFP64>(lm, p.mt, p.nt, a, grid, threads, lds, st);
   } else {
     switch (pb.prec) {
-      case kFP64: e = dispatch_kvec<float, kFP64>(kvec, p.mt, p.nt, a, grid, threads, p.lds_bytes, st); break;
-      case kFP32: e = dispatch_kvec<float, kFP32>(kvec, p.mt, p.nt, a, grid, threads, p.lds_bytes, st); break;
-      case kBF16: e = dispatch_kvec<float, kBF16>(kvec, p.mt, p.nt, a, grid, threads, p.lds_bytes, st); break;
-      default: e = dispatch_kvec<float, kBF16X3>(kvec, p.mt, p.nt, a, grid, threads, p.lds_bytes, st); break;
+      case kFP64: e = dispatch_lm<float, kFP64>(lm, p.mt, p.nt, a, grid, threads, lds, st); break;
+      case kFP32: e = dispatch_lm<float, kFP32>(lm, p.mt, p.nt, a, grid, threads, lds, st); break;
+      case kBF16: e = dispatch_lm<float, kBF16>(lm, p.mt, p.nt, a, grid, threads, lds, st); break;
+      default: e = dispatch_lm<float, kBF16X3>(lm, p.mt, p.nt, a, grid, threads, lds, st); break;
     }
   }
   if (e != hipSuccess) return e;

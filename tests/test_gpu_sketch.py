@@ -77,6 +77,19 @@ def test_sketch_seed_draw_and_graph_paths():
     assert not torch.equal(y1, y4)
 
 
+def test_sketch_unaligned_view_mode0():
+    """Mode 0 of a view at an odd offset cannot use 16-byte row loads."""
+    need_gpu()
+    import paper_2507_23207_amd as krp
+    n = 32 * 24 * 20
+    base = torch.randn(n + 1, dtype=torch.float32, device="cuda")
+    xd = base[1:].view(20, 24, 32).permute(2, 1, 0)
+    x = to_host(xd)
+    banner("sketch unaligned mode 0")
+    y = krp.sketch(xd, [0], [13], prec="bf16x3")[0]
+    assert rel(to_host(y), _oracle_sketch(x, 0, 13)) <= 1e-5
+
+
 def test_sketch_unaligned_view():
     """A tensor view at an odd offset takes the scalar-load path."""
     need_gpu()
