@@ -28,14 +28,17 @@ constexpr int kQrWaves = 8;
 constexpr int kQrThreads = 64 * kQrWaves;
 constexpr int kQrCh = 64;                 // rows per streamed chunk
 constexpr int kQrPitch = kQrMaxEll + 1;   // pitch of chunks, G and R^{-1}
-constexpr int kQrCPitch = kQrMaxEll + 2;  // pitch of the combined rows (ell + 1 columns)
+// Pivot rows of the elimination: 8 chunks of 16 columns, chunk stride 18
+// (the chunks start on distinct LDS banks).
+constexpr int kQrCPitch = 8 * 18;
+__device__ __forceinline__ int cpos(int c) { return (c >> 4) * 18 + (c & 15); }
 constexpr int kQrMaxTasks = 16;           // matrix-core tasks (<= 2 per wave)
-constexpr int kQrColsPerThread = 9;       // ceil(65 / 8): combined columns per thread
 
 struct QrShared {
   double chunk_in[kQrCh * kQrPitch];   // rows of the streamed matrix (row-major); Gram partials at the end
   double chunk_out[kQrCh * kQrPitch];  // rows of the product with R^{-1} (row-major)
-  double c[kQrMaxEll * kQrCPitch];     // combined rows [L^{-1} | U] of the elimination
+  __align__(16) double c[2 * kQrCPitch];  // pivot rows of the elimination (by step parity)
+  double diag_u[kQrMaxEll];            // U[i][i] of the elimination
   double g[kQrMaxEll * kQrPitch];      // Gram matrix; after a successful elimination R^{-1}
   double diag_ref[kQrMaxEll];
   double tr;
@@ -80,8 +83,10 @@ __device__ void qr_stream(const double* src, double* dst, int64_t n, int ell, vo
   Pol::Acc gacc[2];
   gacc[0] = Pol::zero();
   gacc[1] = Pol::zero();
-  double pre[8];
-  auto load_chunk = [&](int ch) {
+  // two chunks in flight: the loads of chunk ch + 2 are issued as soon as
+  // chunk ch has been stored to LDS
+  double preA[8], preB[8];
+  auto load_chunk = [&](int ch, double (&pre)[8]) {
     const int64_t row = (int64_t)ch * kQrCh + lr;
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
@@ -89,15 +94,16 @@ __device__ void qr_stream(const double* src, double* dst, int64_t n, int ell, vo
       pre[j] = (row < n && c < ell) ? src[row + n * c] : 0.0;
     }
   };
-  load_chunk(0);
-  for (int ch = 0; ch < nch; ++ch) {
+  load_chunk(0, preA);
+  if (nch > 1) load_chunk(1, preB);
+  auto body = [&](int ch, double (&pre)[8]) {
     // store the prefetched rows (columns up to lp, zeros past ell and n)
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
       const int c = cg + 8 * j;
       if (c < lp) sh.chunk_in[lr * kQrPitch + c] = pre[j];
     }
-    if (ch + 1 < nch) load_chunk(ch + 1);
+    if (ch + 2 < nch) load_chunk(ch + 2, pre);
     __syncthreads();
     const double* gsrc = sh.chunk_in;
     if (APPLY) {
@@ -175,6 +181,10 @@ __device__ void qr_stream(const double* src, double* dst, int64_t n, int ell, vo
       }
     }
     __syncthreads();
+  };
+  for (int ch = 0; ch < nch; ch += 2) {
+    body(ch, preA);
+    if (ch + 1 < nch) body(ch + 1, preB);
   }
   if (GRAM) {
     double* part = sh.chunk_in;  // kQrMaxTasks x 256 partial tiles
@@ -210,71 +220,104 @@ __device__ void qr_stream(const double* src, double* dst, int64_t n, int ell, vo
   }
 }
 
-// R^{-1} of G + shift I into sh.g by symmetric elimination of [I | G] rows.
+// R^{-1} of G + shift I into sh.g by symmetric elimination of the rows of
+// [I | G] (width 2 ell).  Every row takes the full update
+//   row_i -= (U[k][i] / U[k][k]) row_k   for i > k
+// at step k: the identity part of row k is zero beyond column k and the part
+// of row i left of its diagonal is never read, so no column masks are needed.
+// All eight waves take part (lane = 8 rows x 8 column chunks of 16 per
+// wave): a lane owns one row x 16 columns in registers, and only the pivot
+// row of the next step goes through LDS.  Columns past 2 ell carry values
+// that are never used, so no step needs a per-column predicate.
 // Returns false (uniformly) on a pivot breakdown, leaving sh.g untouched.
+constexpr int kElimLanes = 512;
+constexpr int kElimMaxR = 1;   // rows per lane
+constexpr int kElimMaxC = 16;  // columns per lane (8 chunks cover 2 ell <= 128)
+
 __device__ bool qr_elim(int ell, double shift, QrShared& sh) {
   const int tid = threadIdx.x;
-  const int tpr = kQrThreads / ell;                // threads per row (>= 8)
-  const int cpt = (ell + 1 + tpr - 1) / tpr;       // combined columns per thread (<= 9)
-  const int row = tid / tpr, sub = tid % tpr;
-  const bool has_row = row < ell;
-  const int c0 = sub * cpt;
-  double cv[kQrColsPerThread];
+  const int width = 2 * ell;
+  constexpr int R = 1;
+  constexpr int C = kElimMaxC;
+  const bool part = tid < kElimLanes;
+  const int grp = tid / 8, ch = tid % 8;
+  const int r0 = grp * R, c0 = ch * C;
+  double cv[kElimMaxR][kElimMaxC];
   __syncthreads();  // a previous elimination may still be reading sh.c
-  // combined row i: columns c <= i hold L^{-1}[i][c] (identity at first),
-  // columns c > i hold the Schur complement entry (i, c - 1)
+  // combined row i: columns 0..ell-1 hold L^{-1}[i][.] (identity at first),
+  // columns ell..2 ell - 1 hold the Schur complement row U[i][.]
 #pragma unroll
-  for (int q = 0; q < kQrColsPerThread; ++q) {
-    const int c = c0 + q;
-    double v = 0.0;
-    if (has_row && q < cpt && c <= ell) {
-      if (c <= row) v = (c == row) ? 1.0 : 0.0;
-      else v = sh.g[row * kQrPitch + c - 1] + ((c - 1 == row) ? shift : 0.0);
-      sh.c[row * kQrCPitch + c] = v;
+  for (int r = 0; r < kElimMaxR; ++r) {
+    const int i = r0 + r;
+#pragma unroll
+    for (int q = 0; q < kElimMaxC; ++q) {
+      const int c = c0 + q;
+      double v = 0.0;
+      if (part && r < R && i < ell && c < width) {
+        if (c < ell) v = (c == i) ? 1.0 : 0.0;
+        else v = sh.g[i * kQrPitch + c - ell] + ((c - ell == i) ? shift : 0.0);
+        if (i == 0) sh.c[cpos(c)] = v;  // the first pivot row
+      }
+      cv[r][q] = v;
     }
-    cv[q] = v;
   }
   if (tid < ell) sh.diag_ref[tid] = sh.g[tid * kQrPitch + tid] + shift;
   __syncthreads();
+  // No early exit: a breakdown is recorded and tested after the loop (the
+  // remaining steps then run on non-finite values that are discarded), and
+  // the updates cover the whole register block unconditionally (multiplier 0
+  // for rows not below the pivot; columns past the block's width are never
+  // stored), which keeps every step free of divergent branches.
   bool ok = true;
-  const int rl = has_row ? row + 1 : 0;
   for (int k = 0; k < ell; ++k) {
-    // every read of the step is issued before any use
-    const double* ck = &sh.c[k * kQrCPitch];
-    const double piv = ck[k + 1], ref = sh.diag_ref[k], num = ck[rl];
-    double rk[kQrColsPerThread];
+    const double* ck = &sh.c[(k & 1) * kQrCPitch];
+    const double piv = ck[cpos(ell + k)], ref = sh.diag_ref[k];
+    ok = ok && (piv > 1e-14 * ref) && isfinite(piv);
+    if (part) {
+      double rk[kElimMaxC], num[kElimMaxR];
 #pragma unroll
-    for (int q = 0; q < kQrColsPerThread; ++q) rk[q] = ck[min(c0 + q, ell)];
-    if (!(piv > 1e-14 * ref) || !isfinite(piv)) {
-      ok = false;
-      break;
-    }
-    if (has_row && row > k) {
-      const double l = num / piv;
-#pragma unroll
-      for (int q = 0; q < kQrColsPerThread; ++q) {
-        const int c = c0 + q;
-        if (q < cpt && c <= ell && (c <= k || c > row)) cv[q] -= l * rk[q];
+      for (int q = 0; q < kElimMaxC; q += 2) {
+        const double2 t = *reinterpret_cast<const double2*>(&ck[ch * 18 + q]);
+        rk[q] = t.x;
+        rk[q + 1] = t.y;
       }
-      if (row == k + 1) {
 #pragma unroll
-        for (int q = 0; q < kQrColsPerThread; ++q) {
-          const int c = c0 + q;
-          if (q < cpt && c <= ell) sh.c[row * kQrCPitch + c] = cv[q];
+      for (int r = 0; r < kElimMaxR; ++r) num[r] = ck[cpos(ell + min(r0 + r, ell - 1))];
+      const double rp = 1.0 / piv;
+#pragma unroll
+      for (int r = 0; r < kElimMaxR; ++r) {
+        const double l = (r0 + r > k && r0 + r < ell) ? num[r] * rp : 0.0;
+#pragma unroll
+        for (int q = 0; q < kElimMaxC; ++q) cv[r][q] -= l * rk[q];
+      }
+      // the next pivot row is final now
+      const int rn = k + 1 - r0;
+      if (rn >= 0 && rn < R && k + 1 < ell) {
+        double* cn = &sh.c[((k + 1) & 1) * kQrCPitch + ch * 18];
+#pragma unroll
+        for (int q = 0; q < kElimMaxC; q += 2) {
+          *reinterpret_cast<double2*>(&cn[q]) = make_double2(cv[0][q], cv[0][q + 1]);
         }
       }
     }
+    if (tid == 0) sh.diag_u[k] = piv;
     __syncthreads();
   }
   if (!ok) return false;
   // R^{-1}[m][i] = L^{-1}[i][m] / sqrt(U[i][i]) for m <= i, zero elsewhere
   // (including the padding up to the next multiple of 16)
-  if (has_row) {
-    const double dinv = 1.0 / sqrt(sh.c[row * kQrCPitch + row + 1]);
+  if (part) {
 #pragma unroll
-    for (int q = 0; q < kQrColsPerThread; ++q) {
-      const int c = c0 + q;
-      if (q < cpt && c <= row) sh.g[c * kQrPitch + row] = cv[q] * dinv;
+    for (int r = 0; r < kElimMaxR; ++r) {
+      const int i = r0 + r;
+      if (r < R && i < ell) {
+        const double dinv = 1.0 / sqrt(sh.diag_u[i]);
+#pragma unroll
+        for (int q = 0; q < kElimMaxC; ++q) {
+          const int m = c0 + q;
+          if (q < C && m <= i) sh.g[m * kQrPitch + i] = cv[r][q] * dinv;
+        }
+      }
     }
   }
   const int lp = (ell + 15) / 16 * 16;

@@ -14,7 +14,7 @@ namespace krp {
 
 namespace {
 
-constexpr int kEigThreads = 256;
+constexpr int kEigThreads = 512;
 constexpr int kGramThreads = 256;
 constexpr int kEigMax = 64;
 
@@ -65,7 +65,7 @@ __device__ __forceinline__ void wave_sync() {
 // Sweeps stop when the off-diagonal Frobenius norm is below 1e-13 of the
 // diagonal's.  With v_init, the iteration starts from A = V0^T A_in V0,
 // V = V0 (a warm start from the eigenvectors of a nearby matrix).
-constexpr int kJTasks = 4;  // 2x2 tasks per thread: ceil(32 / (256 / 32))
+constexpr int kJTasks = 2;  // 2x2 tasks per thread: ceil(32 / (512 / 32))
 constexpr int kJPitch = kEigMax + 2;  // even, so 2-element pairs are 16-byte aligned
 
 // 1 / sqrt(x) and 1 / x for positive normal x: hardware estimate plus two
