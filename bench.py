@@ -30,6 +30,9 @@ if ROOT not in sys.path:
 
 METRIC = "KRP-sketch tensor GB/s (% HBM peak); STHOSVD time mixed vs FP64 at equal error"
 HBM_PEAK_GBS = 8000.0
+COPY_ELEMS = 128 * 1024 * 1024  # fp32 elements of the counter-calibration copy (512 MiB)
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sketch_mode1_512x3_bf16x3_traffic.txt")
+SKETCH_SRC = os.path.join(ROOT, "paper_2507_23207_amd", "csrc", "sketch.hip")
 
 
 def parse():
@@ -43,6 +46,8 @@ def parse():
     ap.add_argument("--dims", default="512,512,512")
     ap.add_argument("--rank", type=int, default=32)
     ap.add_argument("--oversample", type=int, default=8)
+    ap.add_argument("--pmc-probe", action="store_true",
+                    help="only run a 512 MiB copy and the dominant sketch launch (for counter runs)")
     return ap.parse_args()
 
 
@@ -92,6 +97,29 @@ def gpu_ms(fn, reps, stream):
     b.record(stream)
     torch.cuda.synchronize()
     return a.elapsed_time(b) / reps
+
+
+def source_hash(path):
+    import hashlib
+    with open(path, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def measured_traffic(prec):
+    """HBM bytes per launch of the dominant sketch from the committed counter
+    runs, or None when they are missing or were taken on other kernel source."""
+    try:
+        kv = {}
+        with open(TRAFFIC_FILE) as f:
+            for line in f:
+                if "=" in line and not line.startswith("#"):
+                    k, v = line.strip().split("=", 1)
+                    kv[k.strip()] = v.strip()
+        if kv.get("sketch_source_sha256_16") != source_hash(SKETCH_SRC) or kv.get("prec") != prec:
+            return None
+        return float(kv["traffic_bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
+        return None
 
 
 def cpu_baseline(x_np, ranks, p, min_seconds=10.0):
@@ -146,6 +174,21 @@ def main():
                               dtype=torch.float32, device="cuda")
     torch.cuda.synchronize()
     stream = torch.cuda.current_stream()
+
+    if args.pmc_probe:
+        # Three plain copies of 512 MiB (the counter calibration) and three
+        # launches of the dominant sketch, nothing else; run under
+        # rocprofv3 --pmc FETCH_SIZE (then WRITE_SIZE).
+        src = torch.empty(COPY_ELEMS, dtype=torch.float32, device="cuda").fill_(1.0)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        for _ in range(3):
+            dst.copy_(src)
+        for _ in range(3):
+            krp.sketch(x, [0], [ells[0]], prec=args.prec, graph=False)
+        torch.cuda.synchronize()
+        print("pmc probe done", flush=True)
+        return
 
     # --- the step: mixed-precision STHOSVD with truncation -------------------
     def step():
@@ -204,7 +247,7 @@ def main():
                    "dims": dims, "rank": args.rank, "ell": ells[0], "prec": args.prec,
                    "storage": "f32", "truncate": True, "algorithmic_bytes_per_step": step_bytes},
         "roofline": {"bound": "hbm", "achieved": dom["gbps"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": dom["gbps"] / HBM_PEAK_GBS, "traffic": None,
+                     "frac": dom["gbps"] / HBM_PEAK_GBS, "traffic": measured_traffic(args.prec),
                      "kernel": "krp_sketch of mode 1 of X (MTTKRP kernel + its reduction)",
                      "bytes_per_launch": dom["bytes"], "ms_per_launch": dom["ms"]},
         "cpu_baseline": cpu,
