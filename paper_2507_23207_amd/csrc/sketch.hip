@@ -492,6 +492,8 @@ hipError_t dispatch_lm(int lm, int mt, int nt, const SketchArgs& args, dim3 grid
 
 }  // namespace
 
+constexpr int64_t kMaxWaveSteps = 64;
+
 SketchPlan plan_sketch(const SketchProblem& pb, const SketchTile& tile) {
   SketchPlan p{};
   int64_t stride[kMaxDims];
@@ -552,6 +554,11 @@ SketchPlan plan_sketch(const SketchProblem& pb, const SketchTile& tile) {
     o_per = (p.o_total + ranges - 1) / ranges;
   }
   o_per = std::max<int64_t>(1, std::min(o_per, p.o_total));
+  // A wave accumulates at most kMaxWaveSteps outer steps in its fp32 (or
+  // policy) accumulators before the partial goes to the fp64 reduction: the
+  // rounding error of a long fp32 sum grows with its length, and long sums
+  // (e.g. 64^5 tensors, 64^4 terms per output) would otherwise cost accuracy.
+  o_per = std::min<int64_t>(o_per, (int64_t)kMaxWaveSteps * p.wo);
   // Keep the LDS factor tables under 64 KiB.
   for (;;) {
     int64_t rows = 32, period = 1;
