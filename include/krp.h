@@ -70,7 +70,14 @@ enum {
 /* krp_opts.flags */
 enum {
   KRP_FLAG_NO_GRAPH = 1,   /* launch kernels directly instead of a cached HIP graph */
-  KRP_FLAG_AUTOTUNE = 2    /* time candidate tilings on first use of a shape */
+  KRP_FLAG_AUTOTUNE = 2    /* time candidate sketch tilings on first use of a shape (dims, mode,
+                              ell, precision, storage, alignment) on the call's stream and keep the
+                              fastest; results are kept per process and in the JSON file
+                              $KRP_TUNE_CACHE (default $HOME/.cache/libkrp/sketch_tiles.json).
+                              Tuned tilings never need more workspace than the default ones;
+                              tuning is skipped while the stream is being captured.  The
+                              tiling changes only the order of the fp64 reduction of partial
+                              sums, i.e. results at the rounding level. */
 };
 
 typedef struct krp_opts {

@@ -65,14 +65,14 @@ def _stream(x):
 
 
 def _opts(prec, seed, draw, truncate=False, graph=True, order=None, workspace=None,
-          status=None, want_err=False):
+          status=None, want_err=False, autotune=False):
     o = _capi.KrpOpts()
     _capi.lib().krp_opts_default(ctypes.byref(o))
     o.seed = int(seed)
     o.draw = int(draw)
     o.prec = PREC[prec] if isinstance(prec, str) else int(prec)
     o.truncate = 1 if truncate else 0
-    o.flags = 0 if graph else _capi.KRP_FLAG_NO_GRAPH
+    o.flags = (0 if graph else _capi.KRP_FLAG_NO_GRAPH) | (_capi.KRP_FLAG_AUTOTUNE if autotune else 0)
     keep = []
     if order is not None:
         arr = _capi.i32_array(order)
@@ -97,14 +97,17 @@ def _check_tensor(x):
         raise ValueError("tensor must have Kolda (column-major) strides; use kolda(x)")
 
 
-def sketch(x, modes, ell, prec="fp32", seed=2507, draw=0, graph=True):
-    """KRP sketches Y_j = X_(m_j) (KRP of the other factors); krp_sketch."""
+def sketch(x, modes, ell, prec="fp32", seed=2507, draw=0, graph=True, autotune=False):
+    """KRP sketches Y_j = X_(m_j) (KRP of the other factors); krp_sketch.
+
+    ``autotune``: time the candidate tilings on first use of each shape and keep
+    the fastest (KRP_FLAG_AUTOTUNE; cached in $KRP_TUNE_CACHE)."""
     torch = _torch()
     _check_tensor(x)
     modes = [int(m) for m in modes]
     ell = [int(v) for v in ell] if hasattr(ell, "__len__") else [int(ell)] * len(modes)
     ys = [torch.empty((l, x.shape[m]), dtype=x.dtype, device=x.device).t() for m, l in zip(modes, ell)]
-    o, _, keep = _opts(prec, seed, draw, graph=graph)
+    o, _, keep = _opts(prec, seed, draw, graph=graph, autotune=autotune)
     rc = _capi.lib().krp_sketch(ctypes.c_void_p(x.data_ptr()), _dtype_code(x), x.dim(),
                                 _capi.i64_array(x.shape), len(modes), _capi.i32_array(modes),
                                 _capi.i32_array(ell), ctypes.byref(o),
@@ -114,14 +117,14 @@ def sketch(x, modes, ell, prec="fp32", seed=2507, draw=0, graph=True):
 
 
 def _tucker(fn, x, ranks, oversample, prec, seed, draw, truncate, rel_err, graph, order,
-            workspace, status):
+            workspace, status, autotune=False):
     _check_tensor(x)
     d = x.dim()
     ranks = [int(r) for r in ranks]
     ells = [r + int(oversample) for r in ranks]
     core = empty_kolda(ells, x.dtype, x.device)
     qs = [_torch().empty((l, n), dtype=x.dtype, device=x.device).t() for n, l in zip(x.shape, ells)]
-    o, err, keep = _opts(prec, seed, draw, truncate, graph, order, workspace, status, rel_err)
+    o, err, keep = _opts(prec, seed, draw, truncate, graph, order, workspace, status, rel_err, autotune)
     cdims = (ctypes.c_int64 * d)()
     rc = fn(ctypes.c_void_p(x.data_ptr()), _dtype_code(x), d, _capi.i64_array(x.shape),
             _capi.i32_array(ranks), int(oversample), ctypes.byref(o), ctypes.c_void_p(core.data_ptr()),
@@ -138,17 +141,17 @@ def _tucker(fn, x, ranks, oversample, prec, seed, draw, truncate, rel_err, graph
 
 
 def hosvd(x, ranks, oversample, prec="fp32", seed=2507, draw=0, truncate=False, rel_err=False,
-          graph=True, workspace=None, status=None):
+          graph=True, workspace=None, status=None, autotune=False):
     """Randomized HOSVD with KRPs (Algorithm 7); krp_hosvd.  Returns (core, [Q_i], rel_err)."""
     return _tucker(_capi.lib().krp_hosvd, x, ranks, oversample, prec, seed, draw, truncate, rel_err,
-                   graph, None, workspace, status)
+                   graph, None, workspace, status, autotune)
 
 
 def sthosvd(x, ranks, oversample, prec="fp32", seed=2507, draw=0, truncate=False, rel_err=False,
-            graph=True, order=None, workspace=None, status=None):
+            graph=True, order=None, workspace=None, status=None, autotune=False):
     """Randomized STHOSVD with KRPs (Algorithm 8); krp_sthosvd.  Returns (core, [Q_i], rel_err)."""
     return _tucker(_capi.lib().krp_sthosvd, x, ranks, oversample, prec, seed, draw, truncate, rel_err,
-                   graph, order, workspace, status)
+                   graph, order, workspace, status, autotune)
 
 
 def hankel_lowrank(s, h, m, n, r, ell_r, ell_l=0, prec="fp32", seed=2507, draw=0, graph=True):

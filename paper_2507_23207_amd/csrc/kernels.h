@@ -50,6 +50,11 @@ struct SketchPlan {
 
 SketchPlan plan_sketch(const SketchProblem& pb, const SketchTile& tile);
 
+// The fastest tiling of this sketch shape: from the tuning table (memory, then
+// the JSON cache file), else timed now on pb.x over the candidate tilings on
+// `st` (not while `st` is capturing; the default tile is returned then).
+SketchTile tuned_tile(const SketchProblem& pb, hipStream_t st);
+
 // Launches the sketch of one mode: partial sums into `partial` (workspace of
 // plan.partial_bytes), then the deterministic reduction into y64 (fp64,
 // n_rows x ell column-major) and, if y_out is not null, into y_out in the

@@ -160,6 +160,11 @@ int plan_tucker(bool sthosvd, int dtype, int d, const int64_t* dims, const int32
   return KRP_OK;
 }
 
+std::string plan_key(const SketchPlan& p) {
+  return std::to_string(p.mt) + "," + std::to_string(p.wm) + "," + std::to_string(p.wo) + "," +
+         std::to_string(p.o_per_wg);
+}
+
 std::string tucker_key(const TuckerSetup& s, const krp_opts& o, const void* X, const void* core,
                        void* const* Q, const void* ws, const int* status, bool want_err) {
   std::string k = s.sthosvd ? "sthosvd" : "hosvd";
@@ -171,6 +176,7 @@ std::string tucker_key(const TuckerSetup& s, const krp_opts& o, const void* X, c
        "|tr=" + std::to_string(o.truncate) + "|err=" + std::to_string(want_err ? 1 : 0) +
        "|X=" + ptr_key(X) + "|core=" + ptr_key(core) + "|ws=" + ptr_key(ws) + "|" +
        "|st=" + ptr_key(status);
+  for (int i = 0; i < s.n_sketch; ++i) k += "|t=" + plan_key(s.spl[i]);  // tilings (tuned or not)
   return k;
 }
 
@@ -291,6 +297,43 @@ int enqueue_tucker(const TuckerSetup& s, const krp_opts& o, const void* X, void*
   return KRP_OK;
 }
 
+// Replaces the sketch plans by autotuned ones (their partial sums never need
+// more workspace than the default plans').  Sketches of X are timed on X; the
+// STHOSVD sketches of partial cores on a zero-filled stand-in of the core's
+// size, since their input only exists once the sweep runs.
+int autotune_tucker(TuckerSetup& s, bool sthosvd, const void* X, hipStream_t st) {
+  size_t stand_in = 0;
+  for (int step = 0; step < s.n_sketch; ++step) {
+    if (step == 0 || !sthosvd) continue;
+    const SketchProblem& pb = s.spb[step];
+    int64_t e = 1;
+    for (int k = 0; k < pb.d; ++k) e *= pb.dims[k];
+    stand_in = std::max(stand_in, (size_t)e * (pb.x_is_double ? 8 : 4));
+  }
+  void* buf = nullptr;
+  if (stand_in) {
+    hipError_t e = hipMalloc(&buf, stand_in);
+    if (e == hipSuccess) e = hipMemsetAsync(buf, 0, stand_in, st);
+    if (e != hipSuccess) {
+      if (buf) hipFree(buf);
+      return hip_fail(e, "autotune stand-in");
+    }
+  }
+  for (int step = 0; step < s.n_sketch; ++step) {
+    SketchProblem pb = s.spb[step];
+    pb.x = (step == 0 || !sthosvd) ? X : buf;
+    const SketchTile t = tuned_tile(pb, st);
+    SketchPlan p = plan_sketch(pb, t);
+    if (p.partial_bytes <= s.spl[step].partial_bytes) s.spl[step] = p;
+  }
+  if (buf) {
+    hipError_t e = hipStreamSynchronize(st);
+    hipFree(buf);
+    if (e != hipSuccess) return hip_fail(e, "autotune");
+  }
+  return KRP_OK;
+}
+
 int tucker_entry(bool sthosvd, const void* X, int dtype, int d, const int64_t* dims,
                  const int32_t* rank, int32_t oversample, const krp_opts* opts, void* core,
                  void* const* Q, int64_t* core_dims, void* stream) {
@@ -309,6 +352,7 @@ int tucker_entry(bool sthosvd, const void* X, int dtype, int d, const int64_t* d
   if (core_dims)
     for (int k = 0; k < d; ++k) core_dims[k] = o.truncate ? s.rank[k] : s.ell[k];
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  if (o.flags & KRP_FLAG_AUTOTUNE) KRP_TRY(autotune_tucker(s, sthosvd, X, st));
   char* ws = nullptr;
   KRP_TRY(acquire_workspace(&o, s.total, st, &ws));
   int* status = o.status_dev ? o.status_dev : reinterpret_cast<int*>(ws + s.off_status);
@@ -369,6 +413,10 @@ int krp_sketch(const void* X, int dtype, int d, const int64_t* dims, int nmodes,
     pb.draw = o.draw;
     pb.sketch_id = (uint32_t)m;
     pls[j] = plan_sketch(pb, SketchTile{});
+    if (o.flags & KRP_FLAG_AUTOTUNE) {
+      const SketchPlan t = plan_sketch(pb, tuned_tile(pb, reinterpret_cast<hipStream_t>(stream)));
+      if (t.partial_bytes <= pls[j].partial_bytes) pls[j] = t;
+    }
     part = std::max(part, pls[j].partial_bytes);
   }
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
@@ -379,7 +427,8 @@ int krp_sketch(const void* X, int dtype, int d, const int64_t* dims, int nmodes,
                     "|X=" + ptr_key(X) + "|ws=" + ptr_key(ws) + "|";
   for (int k = 0; k < d; ++k) key += std::to_string(dims[k]) + ",";
   for (int j = 0; j < nmodes; ++j)
-    key += "|" + std::to_string(modes[j]) + "," + std::to_string(ell[j]) + "," + ptr_key(Y[j]);
+    key += "|" + std::to_string(modes[j]) + "," + std::to_string(ell[j]) + "," + ptr_key(Y[j]) + ",t=" +
+           plan_key(pls[j]);
   return run_maybe_graph(key, !(o.flags & KRP_FLAG_NO_GRAPH), st, [&](hipStream_t cs) -> int {
     for (int j = 0; j < nmodes; ++j) {
       KRP_TRY(check(launch_sketch(pbs[j], pls[j], ws, nullptr, Y[j], dtype == KRP_F64, cs), "sketch"));
