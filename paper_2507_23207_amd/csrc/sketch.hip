@@ -255,7 +255,10 @@ __global__ __launch_bounds__(512) void sketch_kernel(SketchArgs a) {
 #pragma unroll
     for (int k = 0; k < kMaxDims; ++k) {
       if (k < a.n_out) {
-        const int rr = toff[k] + (int)((z.dig[k] - lo[k] + a.o_size[k]) % a.o_size[k]);
+        // digit and first digit both lie in [0, o_size): one wrap at most
+        int dd = (int)(z.dig[k] - lo[k]);
+        dd = dd < 0 ? dd + (int)a.o_size[k] : dd;
+        const int rr = toff[k] + dd;
 #pragma unroll
         for (int t = 0; t < NT; ++t) w[t] = w[t] * tab[rr * CP + 16 * t + n];
       }
@@ -325,27 +328,32 @@ __global__ __launch_bounds__(512) void sketch_kernel(SketchArgs a) {
   Odo cur = odo_init(o_begin + w_o);
   if (cur.o < o_end) load_a(bufA, cur);
   // The factor table is drawn while the first slab loads are in flight.
-  // Draw the factor rows (fp64 Gaussians rounded to the working precision).
-  for (int e = threadIdx.x; e < rows_total * CP; e += blockDim.x) {
-    const int r = e / CP, c = e - (e / CP) * CP;
-    const int gc = col0 + c;
-    T v = (T)0;
-    if (gc < a.ell) {
-      if (r < 32) {
-        const int64_t row = f0 + r;
-        if (row < a.n_f) v = factor_value<P>(gauss_entry(a.seed, a.w2_base | (uint64_t)a.fid_f, 0, row, gc));
-      } else {
-        int k = 0;
+  // Draw the factor rows (fp64 Gaussians rounded to the working precision):
+  // only the ell_c real columns of this chunk (one generator call per entry,
+  // the factor and row chosen without branches), then zeros in the padding.
+  const int ncol = min(CP, a.ell - col0);
+  for (int e = threadIdx.x; e < rows_total * ncol; e += blockDim.x) {
+    const int r = e / ncol, c = e - (e / ncol) * ncol;
+    int k = 0;
 #pragma unroll
-        for (int kk = 1; kk < kMaxDims; ++kk)
-          if (kk < a.n_out && r >= toff[kk]) k = kk;
-        const int64_t row = (lo[k] + (r - toff[k])) % a.o_size[k];
-        v = factor_value<P>(gauss_entry(a.seed, a.w2_base | (uint64_t)a.o_fid[k], 0, row, gc));
-      }
-    }
-    tab[e] = v;
+    for (int kk = 1; kk < kMaxDims; ++kk)
+      if (kk < a.n_out && r >= toff[kk]) k = kk;
+    const bool fr = r < 32;
+    const int64_t orow = (lo[k] + (r - toff[k])) % a.o_size[k];
+    const int64_t row = fr ? f0 + r : orow;
+    const uint64_t fid = fr ? (uint64_t)a.fid_f : (uint64_t)a.o_fid[k];
+    T v = (T)0;
+    if (!fr || row < a.n_f) v = factor_value<P>(gauss_entry(a.seed, a.w2_base | fid, 0, row, col0 + c));
+    tab[r * CP + c] = v;
   }
-  __syncthreads();
+  for (int e = threadIdx.x; e < rows_total * (CP - ncol); e += blockDim.x) {
+    const int r = e / (CP - ncol), c = ncol + e % (CP - ncol);
+    tab[r * CP + c] = (T)0;
+  }
+  // LDS-only barrier: the first slab loads stay in flight across it.
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
   while (cur.o < o_end) {
     Odo nxt = cur;
     odo_step(nxt, a.wo);
