@@ -16,20 +16,27 @@ Generator
     0x9E3779B97F4A7C15 and 0xBB67AE8584CAA73B.
 Key
     (seed, 0).
-Counter of entry (row a, column c) of factor ``f`` drawn for sketch ``k``
-    (a, c, draw * 2**32 + k * 2**16 + f, instance).
+Counter of the entries (row a, columns 4j .. 4j+3) of factor ``f`` drawn for sketch ``k``
+    (a, j, draw * 2**32 + k * 2**16 + f, instance).
     ``k`` is the sketched mode (0-based) in the Tucker algorithms, 0xFFFF for
     a factor set shared by all modes; ``f`` is the factor's mode; for the
     block-Hankel sketch f = 0, 1, 2, 3 name Omega1, Omega2, Psi1, Psi2 and
     ``instance`` is the Hankel instance (0 for tensors).
 Transform of the output words (w0, w1, w2, w3)
-    u1 = ((w0 >> 11) + 1) * 2**-53  in (0, 1]
-    k2 = w1 >> 11                   (u2 = k2 * 2**-53 in [0, 1))
-    g  = sqrt(-2 ln u1) * cos(2 pi u2); w2 and w3 are not used.
+    Pair p = 0 uses (w0, w1), pair p = 1 uses (w2, w3); for pair p with words
+    (wu, wv):
+    u1 = ((wu >> 11) + 1) * 2**-53  in (0, 1]
+    k2 = wv >> 11                   (u2 = k2 * 2**-53 in [0, 1))
+    r  = sqrt(-2 ln u1)
+    column 4j + 2p     gets  r * cos(2 pi u2),
+    column 4j + 2p + 1 gets  r * sin(2 pi u2),
+    the two Box-Muller outputs of one (u1, u2), which are independent
+    standard normals.  sin(2 pi u2) is defined as cos(2 pi u2 - pi/2), i.e.
+    ``cos_two_pi((k2 - 2**51) mod 2**53)``, a shift that is exact in integers.
     ``ln`` and ``cos`` are this module's own FMA-free polynomial evaluations
     (below), so that any IEEE-754 binary64 implementation that performs the
-    same correctly rounded +, -, *, / and sqrt in the same order reproduces g
-    bit for bit.
+    same correctly rounded +, -, *, / and sqrt in the same order reproduces
+    every entry bit for bit.
 Working-precision copies
     fp32: RNE to binary32.  bf16: RNE of the fp32 value to bfloat16.
     split bf16 pair: hi = bf16(fp32(g)), lo = bf16(fp32(g) - hi), the
@@ -157,14 +164,29 @@ def cos_two_pi(k2: np.ndarray) -> np.ndarray:
     return np.select([qm == 0, qm == 1, qm == 2], [c, -s, -c], s)
 
 
+def sin_two_pi(k2: np.ndarray) -> np.ndarray:
+    """sin(2 pi k2 2^-53) = cos(2 pi (k2 - 2^51) 2^-53), the shift taken mod 2^53."""
+    k2 = np.asarray(k2, dtype=np.uint64)
+    return cos_two_pi((k2 - np.uint64(1 << 51)) & np.uint64((1 << 53) - 1))
+
+
+def _radius_and_angle(wu, wv):
+    wu = np.asarray(wu, dtype=np.uint64)
+    wv = np.asarray(wv, dtype=np.uint64)
+    u1 = ((wu >> np.uint64(11)) + np.uint64(1)).astype(np.float64) * 2.0 ** -53
+    return np.sqrt(-2.0 * log_unit(u1)), wv >> np.uint64(11)
+
+
 def gaussian_from_words(w0, w1) -> np.ndarray:
-    """The Box-Muller transform of the RNG spec (first two Philox words)."""
-    w0 = np.asarray(w0, dtype=np.uint64)
-    w1 = np.asarray(w1, dtype=np.uint64)
-    u1 = ((w0 >> np.uint64(11)) + np.uint64(1)).astype(np.float64) * 2.0 ** -53
-    k2 = w1 >> np.uint64(11)
-    r = np.sqrt(-2.0 * log_unit(u1))
+    """The cosine output of the Box-Muller transform of one word pair."""
+    r, k2 = _radius_and_angle(w0, w1)
     return r * cos_two_pi(k2)
+
+
+def gaussian_sin_from_words(w0, w1) -> np.ndarray:
+    """The sine output of the Box-Muller transform of one word pair."""
+    r, k2 = _radius_and_angle(w0, w1)
+    return r * sin_two_pi(k2)
 
 
 def counter_word2(draw: int, sketch: int, f: int) -> int:
@@ -176,9 +198,15 @@ def factor(seed: int, draw: int, sketch: int, f: int, rows: int, cols: int,
     """Gaussian factor matrix (rows x cols, float64) of the RNG spec."""
     a = np.arange(rows, dtype=np.uint64)[:, None]
     c = np.arange(cols, dtype=np.uint64)[None, :]
-    w = philox4x64(a, c, np.uint64(counter_word2(draw, sketch, f)),
+    w = philox4x64(a, c >> np.uint64(2), np.uint64(counter_word2(draw, sketch, f)),
                    np.uint64(instance), np.uint64(seed), np.uint64(0))
-    return gaussian_from_words(w[0], w[1]).reshape(rows, cols)
+    w = [np.broadcast_to(x, (rows, cols)) for x in w]
+    second = ((c >> np.uint64(1)) & np.uint64(1)) == 1   # pair p = 1: words (w2, w3)
+    wu = np.where(second, w[2], w[0])
+    wv = np.where(second, w[3], w[1])
+    odd = (c & np.uint64(1)) == 1                        # sine output of the pair
+    g = np.where(odd, gaussian_sin_from_words(wu, wv), gaussian_from_words(wu, wv))
+    return g.reshape(rows, cols)
 
 
 # ---------------------------------------------------------------------------

@@ -211,9 +211,14 @@ __global__ __launch_bounds__(kLsThreads) void hankel_ls_kernel(LsArgs a) {
   const int64_t s = a.t.s[b];
   const int64_t nrow = (int64_t)a.m * s;
   const double* Q = a.q64 + a.t.y_off[b];
-  for (int e = tid; e < a.m * ll; e += kLsThreads) {
-    const int al = e / ll, c = e - (e / ll) * ll;
-    psi2[e] = gauss_entry(a.seed, a.w2_base | 3ull, (uint64_t)b, al, c);
+  const int nq = (ll + 3) >> 2;  // generator calls per factor row (four columns each)
+  for (int e = tid; e < a.m * nq; e += kLsThreads) {
+    const int al = e / nq, jq = e - (e / nq) * nq;
+    double g[4];
+    gauss_quad(a.seed, a.w2_base | 3ull, (uint64_t)b, al, jq, g);
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (4 * jq + u < ll) psi2[al * ll + 4 * jq + u] = g[u];
   }
   constexpr int kU = (L * L + kLsThreads - 1) / kLsThreads;
   double acc[kU];
@@ -228,9 +233,13 @@ __global__ __launch_bounds__(kLsThreads) void hankel_ls_kernel(LsArgs a) {
       const int r = e / lr, j = e - (e / lr) * lr;
       qch[e] = r < rc ? Q[t0 + r + nrow * j] : 0.0;
     }
-    for (int e = tid; e < (int)(a_hi - a_lo + 1) * ll; e += kLsThreads) {
-      const int r = e / ll, c = e - (e / ll) * ll;
-      psi1[e] = gauss_entry(a.seed, a.w2_base | 2ull, (uint64_t)b, a_lo + r, c);
+    for (int e = tid; e < (int)(a_hi - a_lo + 1) * nq; e += kLsThreads) {
+      const int r = e / nq, jq = e - (e / nq) * nq;
+      double g[4];
+      gauss_quad(a.seed, a.w2_base | 2ull, (uint64_t)b, a_lo + r, jq, g);
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if (4 * jq + u < ll) psi1[r * ll + 4 * jq + u] = g[u];
     }
     __syncthreads();
 #pragma unroll

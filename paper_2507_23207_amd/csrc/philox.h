@@ -7,14 +7,17 @@
 // in registers, and nothing is ever stored in HBM.
 //
 // Generator: Philox4x64-10 (Salmon, Moraes, Dror, Shaw, SC'11).
-// Counter of entry (a, c) of factor f for sketch k under draw `draw`:
-//   (a, c, draw << 32 | k << 16 | f, instance), key (seed, 0).
-// Transform of the first two output words (w0, w1):
-//   u1 = ((w0 >> 11) + 1) 2^-53 in (0, 1],  k2 = w1 >> 11,
-//   g  = sqrt(-2 ln u1) cos(2 pi k2 2^-53).
+// Counter of the entries (a, 4j .. 4j+3) of factor f for sketch k under draw
+// `draw`:  (a, j, draw << 32 | k << 16 | f, instance), key (seed, 0).
+// Output words (w0, w1) and (w2, w3) are two Box-Muller pairs (wu, wv):
+//   u1 = ((wu >> 11) + 1) 2^-53 in (0, 1],  k2 = wv >> 11,  r = sqrt(-2 ln u1),
+//   entry 4j + 2p     = r cos(2 pi k2 2^-53),
+//   entry 4j + 2p + 1 = r sin(2 pi k2 2^-53) = r cos(2 pi (k2 - 2^51) 2^-53),
+// for pair p = 0 (w0, w1) and p = 1 (w2, w3).  The cosine and sine outputs of
+// one pair are independent standard normals.
 // ln and cos are evaluated by the fixed sequences below with separately
-// rounded IEEE-754 operations (contraction into FMA is disabled), so the value
-// of g is fully specified by the operation order.
+// rounded IEEE-754 operations (contraction into FMA is disabled), so every
+// entry is fully specified by the operation order.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -148,11 +151,63 @@ __device__ __forceinline__ double cos_two_pi(uint64_t k2) {
   return ((q + 1) & 2) ? -v : v;
 }
 
-__device__ __forceinline__ double gauss_from_words(uint64_t w0, uint64_t w1) {
+// cos and sin of 2 pi k2 2^-53 from one reduction: the sine is the cosine a
+// quarter turn earlier, i.e. the same reduced angle in quadrant q - 1, so both
+// values equal what cos_two_pi gives for k2 and for (k2 - 2^51) mod 2^53.
+__device__ __forceinline__ void sincos_two_pi(uint64_t k2, double& c_out, double& s_out) {
 #pragma clang fp contract(off)
-  const double u1 = (double)((w0 >> 11) + 1ull) * 0x1.0p-53;
-  const double r = __builtin_sqrt(-2.0 * log_unit(u1));
-  return r * cos_two_pi(w1 >> 11);
+  constexpr double kTwoPi = 0x1.921fb54442d18p+2;
+  constexpr double kCos[11] = {1.0,
+                               -1.0 / 2.0,
+                               1.0 / 24.0,
+                               -1.0 / 720.0,
+                               1.0 / 40320.0,
+                               -1.0 / 3628800.0,
+                               1.0 / 479001600.0,
+                               -1.0 / 87178291200.0,
+                               1.0 / 20922789888000.0,
+                               -1.0 / 6402373705728000.0,
+                               1.0 / 2432902008176640000.0};
+  constexpr double kSin[10] = {1.0,
+                               -1.0 / 6.0,
+                               1.0 / 120.0,
+                               -1.0 / 5040.0,
+                               1.0 / 362880.0,
+                               -1.0 / 39916800.0,
+                               1.0 / 6227020800.0,
+                               -1.0 / 1307674368000.0,
+                               1.0 / 355687428096000.0,
+                               -1.0 / 121645100408832000.0};
+  const uint64_t q = (k2 + (1ull << 50)) >> 51;
+  const int64_t rem = (int64_t)k2 - (int64_t)(q << 51);
+  const double f = (double)rem * 0x1.0p-53;
+  const double th = kTwoPi * f;
+  const double z = th * th;
+  double pc = kCos[10];
+#pragma unroll
+  for (int j = 9; j >= 0; --j) {
+    pc = pc * z;
+    pc = pc + kCos[j];
+  }
+  double ps = kSin[9];
+#pragma unroll
+  for (int j = 8; j >= 0; --j) {
+    ps = ps * z;
+    ps = ps + kSin[j];
+  }
+  const double sv = th * ps;
+  const bool odd = (q & 1) != 0;
+  // cosine: quadrant 0: C, 1: -S, 2: -C, 3: S;  sine (quadrant q - 1): 0: S, 1: C, 2: -S, 3: -C
+  const double vc = odd ? sv : pc;
+  const double vs = odd ? pc : sv;
+  c_out = ((q + 1) & 2) ? -vc : vc;
+  s_out = (q & 2) ? -vs : vs;
+}
+
+__device__ __forceinline__ double box_muller_radius(uint64_t wu) {
+#pragma clang fp contract(off)
+  const double u1 = (double)((wu >> 11) + 1ull) * 0x1.0p-53;
+  return __builtin_sqrt(-2.0 * log_unit(u1));
 }
 
 __host__ __device__ __forceinline__ uint64_t counter_word2(uint32_t draw, uint32_t sketch,
@@ -160,12 +215,36 @@ __host__ __device__ __forceinline__ uint64_t counter_word2(uint32_t draw, uint32
   return ((uint64_t)draw << 32) | ((uint64_t)(sketch & 0xFFFFu) << 16) | (uint64_t)(f & 0xFFFFu);
 }
 
-// Entry (row, col) of the factor identified by (seed, w2, instance).
+// Entries (row, 4j), (row, 4j+1), (row, 4j+2), (row, 4j+3) of the factor
+// identified by (seed, w2, instance): one generator call.
+__device__ __forceinline__ void gauss_quad(uint64_t seed, uint64_t w2, uint64_t instance,
+                                           uint64_t row, uint64_t j, double (&g)[4]) {
+#pragma clang fp contract(off)
+  u64x4 c{row, j, w2, instance};
+  const u64x4 w = philox4x64_10(c, seed, 0ull);
+  double c0, s0, c1, s1;
+  sincos_two_pi(w.v1 >> 11, c0, s0);
+  sincos_two_pi(w.v3 >> 11, c1, s1);
+  const double r0 = box_muller_radius(w.v0);
+  const double r1 = box_muller_radius(w.v2);
+  g[0] = r0 * c0;
+  g[1] = r0 * s0;
+  g[2] = r1 * c1;
+  g[3] = r1 * s1;
+}
+
+// Entry (row, col) alone: one generator call, one radius, one of cos / sin.
 __device__ __forceinline__ double gauss_entry(uint64_t seed, uint64_t w2, uint64_t instance,
                                               uint64_t row, uint64_t col) {
-  u64x4 c{row, col, w2, instance};
+#pragma clang fp contract(off)
+  u64x4 c{row, col >> 2, w2, instance};
   const u64x4 w = philox4x64_10(c, seed, 0ull);
-  return gauss_from_words(w.v0, w.v1);
+  const bool second = (col & 2) != 0;
+  const uint64_t wu = second ? w.v2 : w.v0;
+  const uint64_t wv = second ? w.v3 : w.v1;
+  const uint64_t k2 = wv >> 11;
+  const uint64_t k2s = (col & 1) ? ((k2 - (1ull << 51)) & ((1ull << 53) - 1)) : k2;
+  return box_muller_radius(wu) * cos_two_pi(k2s);
 }
 
 }  // namespace krp

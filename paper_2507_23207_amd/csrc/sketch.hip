@@ -70,6 +70,7 @@ __global__ __launch_bounds__(512) void sketch_kernel(SketchArgs a) {
   using T = typename Pol::T;
   using AccT = typename Pol::AccT;
   constexpr int CP = 16 * NT;
+  static_assert(CP % 4 == 0, "column chunks start at multiples of four generator columns");
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* tab = reinterpret_cast<T*>(smem_raw);
 
@@ -328,26 +329,33 @@ __global__ __launch_bounds__(512) void sketch_kernel(SketchArgs a) {
   Odo cur = odo_init(o_begin + w_o);
   if (cur.o < o_end) load_a(bufA, cur);
   // The factor table is drawn while the first slab loads are in flight.
-  // Draw the factor rows (fp64 Gaussians rounded to the working precision):
-  // only the ell_c real columns of this chunk (one generator call per entry,
-  // the factor and row chosen without branches), then zeros in the padding.
+  // Draw the factor rows (fp64 Gaussians rounded to the working precision),
+  // four columns per generator call (the chunk start is a multiple of four),
+  // the factor and row chosen without branches; zeros in the padding.
   const int ncol = min(CP, a.ell - col0);
-  for (int e = threadIdx.x; e < rows_total * ncol; e += blockDim.x) {
-    const int r = e / ncol, c = e - (e / ncol) * ncol;
+  const int nq = (ncol + 3) >> 2;
+  for (int e = threadIdx.x; e < rows_total * nq; e += blockDim.x) {
+    const int r = e / nq, jq = e - (e / nq) * nq;
     int k = 0;
 #pragma unroll
     for (int kk = 1; kk < kMaxDims; ++kk)
       if (kk < a.n_out && r >= toff[kk]) k = kk;
     const bool fr = r < 32;
-    const int64_t orow = (lo[k] + (r - toff[k])) % a.o_size[k];
-    const int64_t row = fr ? f0 + r : orow;
+    int dd = (int)lo[k] + (r - toff[k]);
+    dd = dd >= (int)a.o_size[k] ? dd - (int)a.o_size[k] : dd;
+    const int64_t row = fr ? f0 + r : (int64_t)dd;
     const uint64_t fid = fr ? (uint64_t)a.fid_f : (uint64_t)a.o_fid[k];
-    T v = (T)0;
-    if (!fr || row < a.n_f) v = factor_value<P>(gauss_entry(a.seed, a.w2_base | fid, 0, row, col0 + c));
-    tab[r * CP + c] = v;
+    const bool live = !fr || row < a.n_f;
+    double g[4];
+    gauss_quad(a.seed, a.w2_base | fid, 0, row, (uint64_t)((col0 >> 2) + jq), g);
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int c = 4 * jq + u;
+      tab[r * CP + c] = (live && c < ncol) ? factor_value<P>(g[u]) : (T)0;
+    }
   }
-  for (int e = threadIdx.x; e < rows_total * (CP - ncol); e += blockDim.x) {
-    const int r = e / (CP - ncol), c = ncol + e % (CP - ncol);
+  for (int e = threadIdx.x; e < rows_total * (CP - 4 * nq); e += blockDim.x) {
+    const int r = e / (CP - 4 * nq), c = 4 * nq + e % (CP - 4 * nq);
     tab[r * CP + c] = (T)0;
   }
   // LDS-only barrier: the first slab loads stay in flight across it.

@@ -83,6 +83,50 @@ def test_cos_two_pi_against_mpmath():
     assert vals[1] == 0.0 and vals[3] == 0.0
 
 
+def test_sin_two_pi_against_mpmath():
+    mpmath.mp.dps = 40
+    r = np.random.default_rng(13)
+    k2 = r.integers(0, 2 ** 53, size=500, dtype=np.int64).astype(np.uint64)
+    ours = rng.sin_two_pi(k2)
+    for a, k in zip(ours, k2):
+        ref = mpmath.sin(2 * mpmath.pi * mpmath.mpf(int(k)) / mpmath.mpf(2) ** 53)
+        assert abs(mpmath.mpf(float(a)) - ref) <= 2.5e-16
+    vals = rng.sin_two_pi(np.array([0, 1 << 51, 1 << 52, 3 << 51], dtype=np.uint64))
+    assert vals[0] == 0.0 and vals[1] == 1.0 and vals[2] == 0.0 and vals[3] == -1.0
+
+
+@pytest.mark.parametrize("seed,draw,sketch,f,inst", [(2507, 0, 0, 1, 0), (7, 3, 0xFFFF, 2, 41)])
+def test_factor_layout_against_numpy_philox(seed, draw, sketch, f, inst):
+    """Entry (a, c) comes from the block at counter (a, c div 4, ...), pair (c div 2) mod 2,
+    cosine for even c and sine for odd c: checked against numpy's own Philox words
+    and libm's log / cos / sin."""
+    rows, cols = 7, 13
+    got = rng.factor(seed, draw, sketch, f, rows, cols, inst)
+    w2 = (draw << 32) | (sketch << 16) | f
+    for a in range(rows):
+        for c in range(cols):
+            w = _numpy_philox_block([a, c // 4, w2, inst], [seed, 0])
+            p = (c // 2) % 2
+            u1 = ((w[2 * p] >> 11) + 1) * 2.0 ** -53
+            u2 = (w[2 * p + 1] >> 11) * 2.0 ** -53
+            rad = math.sqrt(-2.0 * math.log(u1))
+            trig = math.sin(2 * math.pi * u2) if c % 2 else math.cos(2 * math.pi * u2)
+            assert abs(got[a, c] - rad * trig) <= 8 * np.finfo(np.float64).eps * max(rad, 1e-300)
+
+
+def test_box_muller_pair_outputs_independent():
+    """The cosine and sine outputs of one word pair are uncorrelated, and so are their squares."""
+    f = rng.factor(2507, 0, 0, 1, 50000, 8)
+    n = f.shape[0] * 4
+    c = f[:, 0::2].ravel()
+    s = f[:, 1::2].ravel()
+    assert abs(np.mean(c * s)) < 5 / math.sqrt(n)
+    # independent N(0,1): E[c^2 s^2] = 1 (it would be 3 if s were c); Var(c^2 s^2) = 8
+    assert abs(np.mean(c * c * s * s) - 1.0) < 5 * math.sqrt(8.0 / n)
+    # outputs of the two pairs of one block are uncorrelated as well
+    assert abs(np.mean(f[:, 0] * f[:, 2])) < 5 / math.sqrt(f.shape[0])
+
+
 def test_gaussian_close_to_libm_box_muller():
     r = np.random.default_rng(4)
     w0 = r.integers(0, 2 ** 63, size=200_000, dtype=np.int64).astype(np.uint64) << np.uint64(1)
