@@ -32,7 +32,9 @@ METRIC = "KRP-sketch tensor GB/s (% HBM peak); STHOSVD time mixed vs FP64 at equ
 HBM_PEAK_GBS = 8000.0
 COPY_ELEMS = 128 * 1024 * 1024  # fp32 elements of the counter-calibration copy (512 MiB)
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sketch_mode1_512x3_bf16x3_traffic.txt")
-SKETCH_SRC = os.path.join(ROOT, "paper_2507_23207_amd", "csrc", "sketch.hip")
+# every source the sketch kernel is compiled from (the measured traffic is void once one changes)
+SKETCH_SRC = tuple(os.path.join(ROOT, "paper_2507_23207_amd", "csrc", f)
+                   for f in ("sketch.hip", "philox.h", "device_common.h", "kernels.h"))
 
 
 def parse():
@@ -99,10 +101,13 @@ def gpu_ms(fn, reps, stream):
     return a.elapsed_time(b) / reps
 
 
-def source_hash(path):
+def source_hash(paths):
     import hashlib
-    with open(path, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for path in paths:
+        with open(path, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def measured_traffic(prec):

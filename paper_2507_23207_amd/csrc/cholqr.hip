@@ -33,6 +33,7 @@ constexpr int kQrPitch = kQrMaxEll + 1;   // pitch of chunks, G and R^{-1}
 constexpr int kQrCPitch = 8 * 18;
 __device__ __forceinline__ int cpos(int c) { return (c >> 4) * 18 + (c & 15); }
 constexpr int kQrMaxTasks = 16;           // matrix-core tasks (<= 2 per wave)
+constexpr int kQrSplitMinChunks = 4;      // row chunks below which the split form is not used
 
 struct QrShared {
   double chunk_in[kQrCh * kQrPitch];   // rows of the streamed matrix (row-major); Gram partials at the end
@@ -64,10 +65,11 @@ __device__ __forceinline__ void tile_pair(int T, int pair, int& ti, int& tj) {
 // kQrCh rows.  APPLY: dst = src R^{-1} (R^{-1} in sh.g), written to dst (and
 // q_out when FINAL).  GRAM: G of the streamed rows (of dst when APPLY) into
 // sh.g (after the stream; both triangles).  dst may alias src: every chunk is
-// read completely before any of its rows is written.
+// read completely before any of its rows is written.  Only the chunks
+// [ch_begin, ch_end) are streamed (ch_end < 0: through the last chunk).
 template <bool APPLY, bool GRAM, bool FINAL>
 __device__ void qr_stream(const double* src, double* dst, int64_t n, int ell, void* q_out,
-                          int out_double, QrShared& sh) {
+                          int out_double, QrShared& sh, int ch_begin = 0, int ch_end = -1) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int nl = lane & 15, g = lane >> 4;
   const int T = (ell + 15) / 16;
@@ -79,7 +81,7 @@ __device__ void qr_stream(const double* src, double* dst, int64_t n, int ell, vo
   const int qper = 16 / ks;
   // chunk loads: row r, columns cg + 8 j
   const int lr = tid % kQrCh, cg = tid / kQrCh;
-  const int nch = (int)((n + kQrCh - 1) / kQrCh);
+  const int nch = ch_end >= 0 ? ch_end : (int)((n + kQrCh - 1) / kQrCh);
   Pol::Acc gacc[2];
   gacc[0] = Pol::zero();
   gacc[1] = Pol::zero();
@@ -94,8 +96,8 @@ __device__ void qr_stream(const double* src, double* dst, int64_t n, int ell, vo
       pre[j] = (row < n && c < ell) ? src[row + n * c] : 0.0;
     }
   };
-  load_chunk(0, preA);
-  if (nch > 1) load_chunk(1, preB);
+  load_chunk(ch_begin, preA);
+  if (ch_begin + 1 < nch) load_chunk(ch_begin + 1, preB);
   auto body = [&](int ch, double (&pre)[8]) {
     // store the prefetched rows (columns up to lp, zeros past ell and n)
 #pragma unroll
@@ -182,7 +184,7 @@ __device__ void qr_stream(const double* src, double* dst, int64_t n, int ell, vo
     }
     __syncthreads();
   };
-  for (int ch = 0; ch < nch; ch += 2) {
+  for (int ch = ch_begin; ch < nch; ch += 2) {
     body(ch, preA);
     if (ch + 1 < nch) body(ch + 1, preB);
   }
@@ -329,19 +331,10 @@ __device__ bool qr_elim(int ell, double shift, QrShared& sh) {
   return true;
 }
 
-__global__ __launch_bounds__(kQrThreads) void cholqr_kernel(int64_t n_default, int ell, const double* y,
-                                                            double* q, void* q_out, int out_double,
-                                                            const int64_t* offsets, const int64_t* nrows,
-                                                            int* status) {
-  __shared__ QrShared sh;
-  const int b = blockIdx.x;
-  const int64_t off = offsets ? offsets[b] : 0;
-  const int64_t n = nrows ? nrows[b] : n_default;
-  const double* src = y + off;
-  double* dst = q + off;
-  char* qo = nullptr;
-  if (q_out) qo = reinterpret_cast<char*>(q_out) + off * (out_double ? 8 : 4);
-
+// The whole CholeskyQR2 (with the shifted CholeskyQR3 fallback) of one matrix
+// on one workgroup: src (n x ell) -> dst (fp64) and qo (storage type).
+__device__ void cholqr_single(int64_t n, int ell, const double* src, double* dst, char* qo,
+                              int out_double, int* status, QrShared& sh) {
   qr_stream<false, true, false>(src, dst, n, ell, nullptr, out_double, sh);
   int clean = 0;  // consecutive unshifted passes
   for (int pass = 0; pass < 6; ++pass) {
@@ -380,7 +373,151 @@ __global__ __launch_bounds__(kQrThreads) void cholqr_kernel(int64_t n_default, i
   if (threadIdx.x == 0) raise_status(status, kStatCholFail);
 }
 
+__global__ __launch_bounds__(kQrThreads) void cholqr_kernel(int64_t n_default, int ell, const double* y,
+                                                            double* q, void* q_out, int out_double,
+                                                            const int64_t* offsets, const int64_t* nrows,
+                                                            int* status) {
+  __shared__ QrShared sh;
+  const int b = blockIdx.x;
+  const int64_t off = offsets ? offsets[b] : 0;
+  const int64_t n = nrows ? nrows[b] : n_default;
+  char* qo = nullptr;
+  if (q_out) qo = reinterpret_cast<char*>(q_out) + off * (out_double ? 8 : 4);
+  cholqr_single(n, ell, y + off, q + off, qo, out_double, status, sh);
+}
+
+// Split form for one tall matrix: the streaming passes run on one workgroup
+// per chunk of kQrCh rows, each leaving the Gram matrix of its rows; the
+// eliminations run on one workgroup that sums those partial Gram matrices in
+// chunk order.  Workspace: partial Gram matrices (chunks x ell x ell), R^{-1}
+// (kQrMaxEll^2, zero padded), and a flag.  Any breakdown (non-finite trace,
+// a pivot failure) sets the flag; the remaining streaming passes are then
+// skipped and the final launch runs the one-workgroup algorithm, with its
+// shifted fallback and status reports, from the untouched Y.
+struct SplitWs {
+  double* gp;
+  double* rinv;
+  int* flag;
+};
+
+__device__ __forceinline__ SplitWs split_ws(void* ws, int64_t n, int ell) {
+  const int64_t nblk = (n + kQrCh - 1) / kQrCh;
+  SplitWs w;
+  w.gp = reinterpret_cast<double*>(ws);
+  w.rinv = w.gp + nblk * ell * ell;
+  w.flag = reinterpret_cast<int*>(w.rinv + kQrMaxEll * kQrMaxEll);
+  return w;
+}
+
+__device__ void load_rinv(const double* rinv, int ell, QrShared& sh) {
+  const int lp = (ell + 15) / 16 * 16;
+  constexpr int kU = kQrMaxEll * kQrMaxEll / kQrThreads;
+  double v[kU];
+#pragma unroll
+  for (int u = 0; u < kU; ++u) {
+    const int e = threadIdx.x + u * kQrThreads;
+    v[u] = e < lp * lp ? rinv[e] : 0.0;
+  }
+#pragma unroll
+  for (int u = 0; u < kU; ++u) {
+    const int e = threadIdx.x + u * kQrThreads;
+    if (e < lp * lp) sh.g[(e / lp) * kQrPitch + e % lp] = v[u];
+  }
+  __syncthreads();
+}
+
+// Gram matrix of the rows of chunk b of src (APPLY: of src R^{-1}, also
+// written to dst) into the partial Gram matrix b.
+template <bool APPLY>
+__global__ __launch_bounds__(kQrThreads) void qr_split_gram_kernel(const double* src, double* dst, int64_t n,
+                                                                   int ell, void* ws) {
+  __shared__ QrShared sh;
+  const SplitWs w = split_ws(ws, n, ell);
+  const int b = blockIdx.x;
+  if (APPLY) {
+    if (*w.flag) return;
+    load_rinv(w.rinv, ell, sh);
+  } else if (b == 0 && threadIdx.x == 0) {
+    *w.flag = 0;
+  }
+  qr_stream<APPLY, true, false>(src, dst, n, ell, nullptr, 0, sh, b, b + 1);
+  double* gp = w.gp + (int64_t)b * ell * ell;
+  for (int e = threadIdx.x; e < ell * ell; e += kQrThreads) gp[e] = sh.g[(e / ell) * kQrPitch + e % ell];
+}
+
+// Sum of the partial Gram matrices, then R^{-1} by the elimination.
+__global__ __launch_bounds__(kQrThreads) void qr_split_elim_kernel(int64_t n, int ell, void* ws) {
+  __shared__ QrShared sh;
+  const SplitWs w = split_ws(ws, n, ell);
+  if (*w.flag) return;
+  const int nblk = (int)((n + kQrCh - 1) / kQrCh);
+  const int tid = threadIdx.x;
+  // chunk order is kept; the loads of eight chunks are issued together
+  for (int e = tid; e < ell * ell; e += kQrThreads) {
+    double t = 0.0;
+    for (int b0 = 0; b0 < nblk; b0 += 8) {
+      double v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = b0 + u < nblk ? w.gp[(int64_t)(b0 + u) * ell * ell + e] : 0.0;
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        if (b0 + u < nblk) t += v[u];
+    }
+    sh.g[(e / ell) * kQrPitch + e % ell] = t;
+  }
+  __syncthreads();
+  if (tid < 64) {
+    const double dg = tid < ell ? sh.g[tid * kQrPitch + tid] : 0.0;
+    const double t = wave_sum(dg);
+    if (tid == 0) sh.tr = t;
+  }
+  __syncthreads();
+  if (!isfinite(sh.tr) || !qr_elim(ell, 0.0, sh)) {
+    if (tid == 0) *w.flag = 1;
+    return;
+  }
+  const int lp = (ell + 15) / 16 * 16;
+  for (int e = tid; e < lp * lp; e += kQrThreads) w.rinv[e] = sh.g[(e / lp) * kQrPitch + e % lp];
+}
+
+// dst = src R^{-1} (final pass, chunk b) or, after a breakdown, the whole
+// one-workgroup algorithm from y on the first workgroup.
+__global__ __launch_bounds__(kQrThreads) void qr_split_final_kernel(const double* y, const double* src,
+                                                                    double* dst, int64_t n, int ell,
+                                                                    void* q_out, int out_double, void* ws,
+                                                                    int* status) {
+  __shared__ QrShared sh;
+  const SplitWs w = split_ws(ws, n, ell);
+  if (*w.flag) {
+    if (blockIdx.x == 0)
+      cholqr_single(n, ell, y, dst, reinterpret_cast<char*>(q_out), out_double, status, sh);
+    return;
+  }
+  load_rinv(w.rinv, ell, sh);
+  qr_stream<true, false, true>(src, dst, n, ell, q_out, out_double, sh, blockIdx.x, blockIdx.x + 1);
+}
+
 }  // namespace
+
+size_t cholqr_split_bytes(int64_t n, int ell) {
+  const int64_t nblk = (n + kQrCh - 1) / kQrCh;
+  return (size_t)(nblk * ell * ell + kQrMaxEll * kQrMaxEll) * sizeof(double) + 256;
+}
+
+hipError_t launch_cholqr_split(int64_t n, int ell, const double* y64, double* q64, void* q_out,
+                               int out_is_double, void* ws, int* status, hipStream_t st) {
+  if (ell > kQrMaxEll || ell < 1 || q64 == y64 || !ws) return hipErrorInvalidValue;
+  if (n < (int64_t)kQrSplitMinChunks * kQrCh)
+    return launch_cholqr(1, n, ell, y64, q64, q_out, out_is_double, nullptr, nullptr, status, st);
+  const int nblk = (int)((n + kQrCh - 1) / kQrCh);
+  hipLaunchKernelGGL(qr_split_gram_kernel<false>, dim3(nblk), dim3(kQrThreads), 0, st, y64, nullptr, n, ell, ws);
+  hipLaunchKernelGGL(qr_split_elim_kernel, dim3(1), dim3(kQrThreads), 0, st, n, ell, ws);
+  hipLaunchKernelGGL(qr_split_gram_kernel<true>, dim3(nblk), dim3(kQrThreads), 0, st, y64, q64, n, ell, ws);
+  hipLaunchKernelGGL(qr_split_elim_kernel, dim3(1), dim3(kQrThreads), 0, st, n, ell, ws);
+  hipLaunchKernelGGL(qr_split_final_kernel, dim3(nblk), dim3(kQrThreads), 0, st, y64, q64, q64, n, ell, q_out,
+                     out_is_double, ws, status);
+  return hipGetLastError();
+}
 
 hipError_t launch_cholqr(int batch, int64_t n, int ell, const double* y64, double* q64, void* q_out,
                          int out_is_double, const int64_t* offsets, const int64_t* nrows, int* status,

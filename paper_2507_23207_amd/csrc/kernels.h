@@ -77,6 +77,13 @@ hipError_t launch_cholqr(int batch, int64_t n, int ell, const double* y64, doubl
                          void* q_out, int out_is_double, const int64_t* offsets,
                          const int64_t* nrows, int* status, hipStream_t st);
 
+// The same for one matrix (q64 distinct from y64), with the streaming passes
+// split over workgroups of row chunks; ws holds cholqr_split_bytes(n, ell)
+// bytes.  Small n falls back to launch_cholqr.
+size_t cholqr_split_bytes(int64_t n, int ell);
+hipError_t launch_cholqr_split(int64_t n, int ell, const double* y64, double* q64, void* q_out,
+                               int out_is_double, void* ws, int* status, hipStream_t st);
+
 // TTM G_new = G x_mode Q^T for a tensor in Kolda order with current sizes
 // dims (dims[mode] = n rows of Q), Q (n x ell, fp64 column-major).
 struct TtmProblem {

@@ -111,6 +111,7 @@ int plan_tucker(bool sthosvd, int dtype, int d, const int64_t* dims, const int32
     pb.sketch_id = (uint32_t)m;
     s.spl[step] = plan_sketch(pb, tile);
     part_max = std::max(part_max, s.spl[step].partial_bytes);
+    part_max = std::max(part_max, cholqr_split_bytes(pb.dims[m], s.ell[m]));  // reused by the QR
     y_max = std::max(y_max, (size_t)(pb.dims[m] * s.ell[m]));
     if (sthosvd) {
       s.ttm_mode[step] = m;
@@ -206,8 +207,9 @@ int enqueue_tucker(const TuckerSetup& s, const krp_opts& o, const void* X, void*
     pb.x_is_double = s.sthosvd ? (cur64 ? 1 : 0) : (x64 ? 1 : 0);
     KRP_TRY(check(launch_sketch(pb, s.spl[step], part, y64, nullptr, 0, st), "sketch"));
     double* q64 = reinterpret_cast<double*>(ws + s.off_q64[m]);
-    KRP_TRY(check(launch_cholqr(1, pb.dims[m], s.ell[m], y64, q64, trunc ? nullptr : Q[m], x64 ? 1 : 0,
-                                nullptr, nullptr, status, st),
+    // the partial-sum buffer of the sketch is free again: workspace of the QR
+    KRP_TRY(check(launch_cholqr_split(pb.dims[m], s.ell[m], y64, q64, trunc ? nullptr : Q[m], x64 ? 1 : 0,
+                                      part, status, st),
                   "cholqr"));
     if (s.sthosvd) {
       TtmProblem tp;

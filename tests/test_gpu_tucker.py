@@ -99,3 +99,43 @@ def test_sthosvd_mode_order_and_determinism():
     assert torch.equal(c1, c2) and all(torch.equal(a, b) for a, b in zip(q1, q2))
     g_ref, q_ref = ot.rsthosvd_krp(x, [5] * 3, 2, order=order)
     assert rel(to_host(c1), g_ref) < 1e-8
+
+
+@pytest.mark.parametrize("algo", ["hosvd", "sthosvd"])
+def test_split_qr_ragged_rows_fp64(algo):
+    """300 x 20 x 18 fp64: the mode-1 QR runs split over row chunks (the last one
+    ragged); factors, core and error agree with the oracle at the fp64 tolerances."""
+    need_gpu()
+    x = low_rank_tensor((300, 20, 18), (6, 6, 6), decay=0.8, noise=1e-3, seed=31)
+    banner(f"split QR {algo} fp64 300x20x18")
+    core, qs, err = _run(algo, to_dev(x, torch.float64), [6] * 3, 4, "fp64", rel_err=True)
+    fn = ot.rhosvd_krp if algo == "hosvd" else ot.rsthosvd_krp
+    g_ref, q_ref = fn(x, [6] * 3, 4)
+    for k in range(3):
+        q = to_host(qs[k])
+        assert np.allclose(q.T @ q, np.eye(10), atol=1e-13)
+        assert subspace_distance(q, q_ref[k]) < 1e-9
+        assert np.max(np.abs(q - q_ref[k])) < 1e-8
+    assert rel(to_host(core), g_ref) < 1e-8
+    e_ref = ot.tucker_rel_error(x, g_ref, q_ref)
+    assert abs(err - e_ref) <= 1e-6 * e_ref
+
+
+@pytest.mark.parametrize("algo", ["hosvd", "sthosvd"])
+def test_split_qr_rank_deficient_takes_shifted_fallback(algo):
+    """256 x 24 x 20 of exact multilinear rank 3 with ell = 6: the mode-1 sketch has rank 3,
+    the split Gram route breaks down, the shifted CholeskyQR3 fallback runs (status bit 1)
+    and the tensor is still recovered to 1e-12."""
+    need_gpu()
+    x = low_rank_tensor((256, 24, 20), (3, 3, 3), noise=0.0, seed=32)
+    banner(f"split QR fallback {algo}")
+    status = torch.zeros(1, dtype=torch.int32, device="cuda")
+    core, qs, _ = _run(algo, to_dev(x, torch.float64), [3] * 3, 3, "fp64", status=status)
+    torch.cuda.synchronize()
+    st = int(status.item())
+    assert st & 1, st
+    assert not st & 6, st
+    q0 = to_host(qs[0])
+    assert np.allclose(q0.T @ q0, np.eye(6), atol=1e-12)
+    e = ot.tucker_rel_error(x, to_host(core), [to_host(q) for q in qs])
+    assert e <= 1e-12, e
