@@ -452,18 +452,31 @@ __global__ __launch_bounds__(kQrThreads) void qr_split_elim_kernel(int64_t n, in
   if (*w.flag) return;
   const int nblk = (int)((n + kQrCh - 1) / kQrCh);
   const int tid = threadIdx.x;
-  // chunk order is kept; the loads of eight chunks are issued together
-  for (int e = tid; e < ell * ell; e += kQrThreads) {
-    double t = 0.0;
-    for (int b0 = 0; b0 < nblk; b0 += 8) {
-      double v[8];
+  // chunk order is kept; a thread's loads of eight chunks for all its
+  // (at most eight) entries are in flight together
+  constexpr int kPer = kQrMaxEll * kQrMaxEll / kQrThreads;
+  double t[kPer];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) v[u] = b0 + u < nblk ? w.gp[(int64_t)(b0 + u) * ell * ell + e] : 0.0;
+  for (int i = 0; i < kPer; ++i) t[i] = 0.0;
+  for (int b0 = 0; b0 < nblk; b0 += 8) {
+    double v[kPer][8];
+#pragma unroll
+    for (int i = 0; i < kPer; ++i) {
+      const int e = tid + i * kQrThreads;
 #pragma unroll
       for (int u = 0; u < 8; ++u)
-        if (b0 + u < nblk) t += v[u];
+        v[i][u] = (e < ell * ell && b0 + u < nblk) ? w.gp[(int64_t)(b0 + u) * ell * ell + e] : 0.0;
     }
-    sh.g[(e / ell) * kQrPitch + e % ell] = t;
+#pragma unroll
+    for (int i = 0; i < kPer; ++i)
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        if (b0 + u < nblk) t[i] += v[i][u];
+  }
+#pragma unroll
+  for (int i = 0; i < kPer; ++i) {
+    const int e = tid + i * kQrThreads;
+    if (e < ell * ell) sh.g[(e / ell) * kQrPitch + e % ell] = t[i];
   }
   __syncthreads();
   if (tid < 64) {

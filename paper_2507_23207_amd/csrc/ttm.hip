@@ -22,6 +22,7 @@ namespace {
 
 constexpr int kTtmWaves = 8;
 constexpr int kSlicePitch = 36;  // 32 reduction slots + padding (elements)
+constexpr int64_t kSplitMaxWaves = 8192;  // below this many one-wave items, the split kernel
 
 struct TtmArgs {
   const void* g;
@@ -72,11 +73,18 @@ __global__ __launch_bounds__(64 * kTtmWaves) void ttm_kernel(TtmArgs a) {
     for (int t = 0; t < NT; ++t) acc[m][t] = Pol::zero();
 
   auto stage = [&](int buf, int64_t k0) {
-    for (int e = threadIdx.x; e < CQ * 32; e += 64 * kTtmWaves) {
+    constexpr int kPer = (CQ * 32 + 64 * kTtmWaves - 1) / (64 * kTtmWaves);
+    T qv[kPer];
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+      const int e = threadIdx.x + u * 64 * kTtmWaves;
       const int c = e / 32, k = e % 32;
-      T v = (T)0;
-      if (c < a.ell && k0 + k < a.n) v = (T)a.q[(k0 + k) + a.n * c];
-      slice[buf][c * kSlicePitch + k] = v;
+      qv[u] = (e < CQ * 32 && c < a.ell && k0 + k < a.n) ? (T)a.q[(k0 + k) + a.n * c] : (T)0;
+    }
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+      const int e = threadIdx.x + u * 64 * kTtmWaves;
+      if (e < CQ * 32) slice[buf][(e / 32) * kSlicePitch + e % 32] = qv[u];
     }
   };
 
@@ -189,6 +197,180 @@ __global__ __launch_bounds__(64 * kTtmWaves) void ttm_kernel(TtmArgs a) {
       }
 }
 
+// Other modes with few items (small cores): one workgroup per (q, p group)
+// and the reduction index split over the waves.  Wave w takes the 32-row
+// slices w, w + 8, ...; it stages its own slice of Q in a private LDS region
+// and keeps the loads of its next slice of G in flight while it multiplies.
+// The eight partial accumulators are summed in wave order through LDS.
+template <typename Tin, int P, int MT, int NT>
+__global__ __launch_bounds__(64 * kTtmWaves) void ttm_split_kernel(TtmArgs a) {
+  using Pol = Policy<P>;
+  using T = typename Pol::T;
+  using AccT = typename Pol::AccT;
+  using Tout = typename std::conditional<P == kFP64, double, float>::type;
+  constexpr int CQ = 16 * MT;
+  constexpr int kStage = CQ * kSlicePitch;
+  extern __shared__ __align__(16) unsigned char ttm_smem[];
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int n = lane & 15, g = lane >> 4;
+  T* st = reinterpret_cast<T*>(ttm_smem) + wave * kStage;
+  const int64_t qq = blockIdx.x / a.p_groups;
+  const int64_t p0 = (int64_t)(blockIdx.x % a.p_groups) * (16 * NT);
+  const Tin* G = reinterpret_cast<const Tin*>(a.g);
+  const int nslices = (int)((a.n + 31) / 32);
+
+  typename Pol::Acc acc[MT][NT];
+#pragma unroll
+  for (int m = 0; m < MT; ++m)
+#pragma unroll
+    for (int t = 0; t < NT; ++t) acc[m][t] = Pol::zero();
+
+  auto load_b = [&](Tin (&x)[NT][8], int s) {
+    const int64_t k0 = (int64_t)s * 32;
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      const int64_t pi = p0 + 16 * t + n;
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const int64_t ai = k0 + 8 * g + j;
+        x[t][j] = (pi < a.P && ai < a.n) ? G[pi + a.P * (ai + a.n * qq)] : (Tin)0;
+      }
+    }
+  };
+  auto step = [&](const Tin (&x)[NT][8], int s) {
+    const int64_t k0 = (int64_t)s * 32;
+    // loads in batches of eight per lane, each batch before its LDS stores
+    // (a few latencies per slice instead of one per element)
+#pragma unroll 1
+    for (int u0 = 0; u0 < CQ / 2; u0 += 8) {
+      T qv[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int e = lane + 64 * (u0 + u);
+        const int c = e / 32, k = e % 32;
+        qv[u] = (c < a.ell && k0 + k < a.n) ? (T)a.q[(k0 + k) + a.n * c] : (T)0;
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int e = lane + 64 * (u0 + u);
+        st[(e / 32) * kSlicePitch + e % 32] = qv[u];
+      }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    typename Pol::Frag af[MT];
+#pragma unroll
+    for (int m = 0; m < MT; ++m) {
+      T v[8];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) v[j] = st[(16 * m + n) * kSlicePitch + 8 * g + j];
+      af[m] = Pol::make(v);
+    }
+    // the next slice's staging must not overtake these reads
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      T v[8];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) v[j] = (T)x[t][j];
+      const typename Pol::Frag bfr = Pol::make(v);
+#pragma unroll
+      for (int m = 0; m < MT; ++m) Pol::mma(acc[m][t], af[m], bfr);
+    }
+  };
+  Tin xa[NT][8], xb[NT][8];
+  int s = wave;
+  if (s < nslices) load_b(xa, s);
+  while (s < nslices) {
+    if (s + kTtmWaves < nslices) load_b(xb, s + kTtmWaves);
+    step(xa, s);
+    s += kTtmWaves;
+    if (s >= nslices) break;
+    if (s + kTtmWaves < nslices) load_b(xa, s + kTtmWaves);
+    step(xb, s);
+    s += kTtmWaves;
+  }
+
+  // sum of the eight partial accumulators, in wave order
+  __syncthreads();
+  AccT* red = reinterpret_cast<AccT*>(ttm_smem);
+  constexpr int E = MT * NT * 4 * 64;
+#pragma unroll
+  for (int m = 0; m < MT; ++m)
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) red[wave * E + ((m * NT + t) * 4 + r) * 64 + lane] = acc[m][t][r];
+  __syncthreads();
+  Tout* out = reinterpret_cast<Tout*>(a.out);
+  for (int e = threadIdx.x; e < E; e += 64 * kTtmWaves) {
+    double sum = 0.0;
+#pragma unroll
+    for (int w = 0; w < kTtmWaves; ++w) sum += (double)red[w * E + e];
+    const int ln = e % 64, mtr = e / 64;
+    const int r = mtr % 4, mt = mtr / 4;
+    const int t = mt % NT, m = mt / NT;
+    const int c = 16 * m + Pol::out_row(ln >> 4, r);
+    const int64_t pi = p0 + 16 * t + (ln & 15);
+    if (pi < a.P && c < a.ell) out[pi + a.P * (c + (int64_t)a.ell * qq)] = (Tout)sum;
+  }
+}
+
+template <typename Tin, int P, int MT, int NT>
+hipError_t ttm_split_go(const TtmArgs& a, hipStream_t st) {
+  using T = typename Policy<P>::T;
+  using AccT = typename Policy<P>::AccT;
+  constexpr size_t stage = (size_t)kTtmWaves * 16 * MT * kSlicePitch * sizeof(T);
+  constexpr size_t red = (size_t)kTtmWaves * MT * NT * 4 * 64 * sizeof(AccT);
+  constexpr size_t lds = stage > red ? stage : red;
+  auto kern = ttm_split_kernel<Tin, P, MT, NT>;
+  if (lds > 65536) {
+    const hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(kern, dim3((unsigned)a.items), dim3(64 * kTtmWaves), lds, st, a);
+  return hipGetLastError();
+}
+
+template <typename Tin, int P, int MT>
+hipError_t ttm_split_nt(int nt, const TtmArgs& a, hipStream_t st) {
+  // fp64 arithmetic: at most two p tiles (the double-buffered fp64 loads and
+  // accumulators of wider groups do not fit in registers)
+  // (four Q tiles: one p tile in fp64, three otherwise)
+  if constexpr (P == kFP64 && MT == 4) {
+    return ttm_split_go<Tin, P, MT, 1>(a, st);
+  } else if constexpr (P == kFP64) {
+    return nt == 1 ? ttm_split_go<Tin, P, MT, 1>(a, st) : ttm_split_go<Tin, P, MT, 2>(a, st);
+  } else if constexpr (MT == 4) {
+    switch (nt) {
+      case 1: return ttm_split_go<Tin, P, MT, 1>(a, st);
+      case 2: return ttm_split_go<Tin, P, MT, 2>(a, st);
+      default: return ttm_split_go<Tin, P, MT, 3>(a, st);
+    }
+  } else {
+    switch (nt) {
+      case 1: return ttm_split_go<Tin, P, MT, 1>(a, st);
+      case 2: return ttm_split_go<Tin, P, MT, 2>(a, st);
+      case 3: return ttm_split_go<Tin, P, MT, 3>(a, st);
+      default: return ttm_split_go<Tin, P, MT, 4>(a, st);
+    }
+  }
+}
+
+template <typename Tin, int P>
+hipError_t ttm_split_dispatch(int tiles_c, int nt, const TtmArgs& a, hipStream_t st) {
+  switch (tiles_c) {
+    case 1: return ttm_split_nt<Tin, P, 1>(nt, a, st);
+    case 2: return ttm_split_nt<Tin, P, 2>(nt, a, st);
+    case 3: return ttm_split_nt<Tin, P, 3>(nt, a, st);
+    default: return ttm_split_nt<Tin, P, 4>(nt, a, st);
+  }
+}
+
 template <typename Tin, int P, bool MODE0, bool KVEC, int MT, int NT>
 hipError_t ttm_go(const TtmArgs& a, hipStream_t st) {
   const unsigned grid = (unsigned)((a.items + kTtmWaves - 1) / kTtmWaves);
@@ -242,9 +424,19 @@ hipError_t launch_ttm(const TtmProblem& pb, void* /*qbuf*/, hipStream_t st) {
   const bool mode0 = (P == 1);
   const int vec = pb.g_is_double ? 2 : 4;
   const bool kvec = mode0 && (a.n % vec == 0) && ((reinterpret_cast<uintptr_t>(pb.g) & 15) == 0);
+  // Few items (small cores): the split kernel, one workgroup per (q, group of
+  // up to 64 p) with the reduction index spread over its waves.
+  bool split = false;
+  int split_nt = 4;
   if (mode0) {
     a.items = (Q + 63) / 64;
     a.p_groups = 1;
+  } else if (Q * ((P + 31) / 32) < kSplitMaxWaves) {
+    split = true;
+    const int nt_max = pb.prec == kFP64 ? (tiles_c >= 4 ? 1 : 2) : (tiles_c >= 4 ? 3 : 4);
+    split_nt = (int)std::min<int64_t>(nt_max, (P + 15) / 16);
+    a.p_groups = (int)((P + 16 * split_nt - 1) / (16 * split_nt));
+    a.items = Q * a.p_groups;
   } else {
     a.p_groups = (int)((P + 31) / 32);
     a.items = Q * a.p_groups;
@@ -252,6 +444,18 @@ hipError_t launch_ttm(const TtmProblem& pb, void* /*qbuf*/, hipStream_t st) {
   if (a.items == 0) return hipSuccess;
   const bool wants_double_out = pb.prec == kFP64;
   if (wants_double_out != (pb.out_is_double != 0)) return hipErrorInvalidValue;
+  if (split) {
+    if (pb.g_is_double) {
+      if (pb.prec != kFP64) return hipErrorInvalidValue;
+      return ttm_split_dispatch<double, kFP64>(tiles_c, split_nt, a, st);
+    }
+    switch (pb.prec) {
+      case kFP64: return ttm_split_dispatch<float, kFP64>(tiles_c, split_nt, a, st);
+      case kFP32: return ttm_split_dispatch<float, kFP32>(tiles_c, split_nt, a, st);
+      case kBF16: return ttm_split_dispatch<float, kBF16>(tiles_c, split_nt, a, st);
+      default: return ttm_split_dispatch<float, kBF16X3>(tiles_c, split_nt, a, st);
+    }
+  }
   if (pb.g_is_double) {
     if (pb.prec != kFP64) return hipErrorInvalidValue;
     return ttm_dispatch<double, kFP64>(mode0, kvec, tiles_c, a, st);
