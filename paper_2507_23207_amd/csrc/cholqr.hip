@@ -387,71 +387,57 @@ __global__ __launch_bounds__(kQrThreads) void cholqr_kernel(int64_t n_default, i
 }
 
 // Split form for one tall matrix: the streaming passes run on one workgroup
-// per chunk of kQrCh rows, each leaving the Gram matrix of its rows; the
-// eliminations run on one workgroup that sums those partial Gram matrices in
-// chunk order.  Workspace: partial Gram matrices (chunks x ell x ell), R^{-1}
-// (kQrMaxEll^2, zero padded), and a flag.  Any breakdown (non-finite trace,
-// a pivot failure) sets the flag; the remaining streaming passes are then
-// skipped and the final launch runs the one-workgroup algorithm, with its
-// shifted fallback and status reports, from the untouched Y.
+// per chunk of kQrCh rows.  The first launch leaves the Gram matrix of each
+// chunk's rows; each later launch sums those partial Gram matrices in chunk
+// order, eliminates (every workgroup the same, deterministic computation, so
+// all of them reach the same R^{-1} or the same breakdown), applies R^{-1} to
+// its chunk and, except in the last pass, leaves the new partial Gram
+// matrices in the other half of the workspace.  On a breakdown (non-finite
+// trace, a failed pivot) workgroup 0 runs the one-workgroup algorithm, with
+// its shifted fallback and status reports, from the untouched Y, and a flag
+// makes the next launch skip its work.
 struct SplitWs {
-  double* gp;
-  double* rinv;
+  double* gp[2];
   int* flag;
 };
 
 __device__ __forceinline__ SplitWs split_ws(void* ws, int64_t n, int ell) {
   const int64_t nblk = (n + kQrCh - 1) / kQrCh;
   SplitWs w;
-  w.gp = reinterpret_cast<double*>(ws);
-  w.rinv = w.gp + nblk * ell * ell;
-  w.flag = reinterpret_cast<int*>(w.rinv + kQrMaxEll * kQrMaxEll);
+  w.gp[0] = reinterpret_cast<double*>(ws);
+  w.gp[1] = w.gp[0] + nblk * ell * ell;
+  w.flag = reinterpret_cast<int*>(w.gp[1] + nblk * ell * ell);
   return w;
 }
 
-__device__ void load_rinv(const double* rinv, int ell, QrShared& sh) {
-  const int lp = (ell + 15) / 16 * 16;
-  constexpr int kU = kQrMaxEll * kQrMaxEll / kQrThreads;
-  double v[kU];
-#pragma unroll
-  for (int u = 0; u < kU; ++u) {
-    const int e = threadIdx.x + u * kQrThreads;
-    v[u] = e < lp * lp ? rinv[e] : 0.0;
-  }
-#pragma unroll
-  for (int u = 0; u < kU; ++u) {
-    const int e = threadIdx.x + u * kQrThreads;
-    if (e < lp * lp) sh.g[(e / lp) * kQrPitch + e % lp] = v[u];
-  }
-  __syncthreads();
-}
-
-// Gram matrix of the rows of chunk b of src (APPLY: of src R^{-1}, also
-// written to dst) into the partial Gram matrix b.
-template <bool APPLY>
-__global__ __launch_bounds__(kQrThreads) void qr_split_gram_kernel(const double* src, double* dst, int64_t n,
-                                                                   int ell, void* ws) {
-  __shared__ QrShared sh;
-  const SplitWs w = split_ws(ws, n, ell);
-  const int b = blockIdx.x;
-  if (APPLY) {
-    if (*w.flag) return;
-    load_rinv(w.rinv, ell, sh);
-  } else if (b == 0 && threadIdx.x == 0) {
-    *w.flag = 0;
-  }
-  qr_stream<APPLY, true, false>(src, dst, n, ell, nullptr, 0, sh, b, b + 1);
-  double* gp = w.gp + (int64_t)b * ell * ell;
+__device__ void store_partial_gram(double* gp, int ell, const QrShared& sh) {
   for (int e = threadIdx.x; e < ell * ell; e += kQrThreads) gp[e] = sh.g[(e / ell) * kQrPitch + e % ell];
 }
 
-// Sum of the partial Gram matrices, then R^{-1} by the elimination.
-__global__ __launch_bounds__(kQrThreads) void qr_split_elim_kernel(int64_t n, int ell, void* ws) {
+// Gram matrix of the rows of chunk b of Y into partial 0.
+__global__ __launch_bounds__(kQrThreads) void qr_split_gram_kernel(const double* y, int64_t n, int ell,
+                                                                   void* ws) {
+  __shared__ QrShared sh;
+  const SplitWs w = split_ws(ws, n, ell);
+  const int b = blockIdx.x;
+  if (b == 0 && threadIdx.x == 0) *w.flag = 0;
+  qr_stream<false, true, false>(y, nullptr, n, ell, nullptr, 0, sh, b, b + 1);
+  store_partial_gram(w.gp[0] + (int64_t)b * ell * ell, ell, sh);
+}
+
+// Sum of the partial Gram matrices `in`, R^{-1} by the elimination, then
+// dst = src R^{-1} on chunk b (FINAL: also q_out) and, unless FINAL, the Gram
+// matrix of the new rows into the partials `1 - in`.
+template <bool FINAL>
+__global__ __launch_bounds__(kQrThreads) void qr_split_pass_kernel(const double* y, const double* src, double* dst,
+                                                                   int64_t n, int ell, void* q_out, int out_double,
+                                                                   void* ws, int in, int* status) {
   __shared__ QrShared sh;
   const SplitWs w = split_ws(ws, n, ell);
   if (*w.flag) return;
   const int nblk = (int)((n + kQrCh - 1) / kQrCh);
   const int tid = threadIdx.x;
+  const double* gp = w.gp[in];
   // chunk order is kept; a thread's loads of eight chunks for all its
   // (at most eight) entries are in flight together
   constexpr int kPer = kQrMaxEll * kQrMaxEll / kQrThreads;
@@ -465,7 +451,7 @@ __global__ __launch_bounds__(kQrThreads) void qr_split_elim_kernel(int64_t n, in
       const int e = tid + i * kQrThreads;
 #pragma unroll
       for (int u = 0; u < 8; ++u)
-        v[i][u] = (e < ell * ell && b0 + u < nblk) ? w.gp[(int64_t)(b0 + u) * ell * ell + e] : 0.0;
+        v[i][u] = (e < ell * ell && b0 + u < nblk) ? gp[(int64_t)(b0 + u) * ell * ell + e] : 0.0;
     }
 #pragma unroll
     for (int i = 0; i < kPer; ++i)
@@ -481,40 +467,27 @@ __global__ __launch_bounds__(kQrThreads) void qr_split_elim_kernel(int64_t n, in
   __syncthreads();
   if (tid < 64) {
     const double dg = tid < ell ? sh.g[tid * kQrPitch + tid] : 0.0;
-    const double t = wave_sum(dg);
-    if (tid == 0) sh.tr = t;
+    const double tr = wave_sum(dg);
+    if (tid == 0) sh.tr = tr;
   }
   __syncthreads();
   if (!isfinite(sh.tr) || !qr_elim(ell, 0.0, sh)) {
-    if (tid == 0) *w.flag = 1;
-    return;
-  }
-  const int lp = (ell + 15) / 16 * 16;
-  for (int e = tid; e < lp * lp; e += kQrThreads) w.rinv[e] = sh.g[(e / lp) * kQrPitch + e % lp];
-}
-
-// dst = src R^{-1} (final pass, chunk b) or, after a breakdown, the whole
-// one-workgroup algorithm from y on the first workgroup.
-__global__ __launch_bounds__(kQrThreads) void qr_split_final_kernel(const double* y, const double* src,
-                                                                    double* dst, int64_t n, int ell,
-                                                                    void* q_out, int out_double, void* ws,
-                                                                    int* status) {
-  __shared__ QrShared sh;
-  const SplitWs w = split_ws(ws, n, ell);
-  if (*w.flag) {
-    if (blockIdx.x == 0)
+    if (blockIdx.x == 0) {
+      if (tid == 0) *w.flag = 1;
       cholqr_single(n, ell, y, dst, reinterpret_cast<char*>(q_out), out_double, status, sh);
+    }
     return;
   }
-  load_rinv(w.rinv, ell, sh);
-  qr_stream<true, false, true>(src, dst, n, ell, q_out, out_double, sh, blockIdx.x, blockIdx.x + 1);
+  const int b = blockIdx.x;
+  qr_stream<true, !FINAL, FINAL>(src, dst, n, ell, q_out, out_double, sh, b, b + 1);
+  if (!FINAL) store_partial_gram(w.gp[1 - in] + (int64_t)b * ell * ell, ell, sh);
 }
 
 }  // namespace
 
 size_t cholqr_split_bytes(int64_t n, int ell) {
   const int64_t nblk = (n + kQrCh - 1) / kQrCh;
-  return (size_t)(nblk * ell * ell + kQrMaxEll * kQrMaxEll) * sizeof(double) + 256;
+  return (size_t)(2 * nblk * ell * ell) * sizeof(double) + 256;
 }
 
 hipError_t launch_cholqr_split(int64_t n, int ell, const double* y64, double* q64, void* q_out,
@@ -523,12 +496,12 @@ hipError_t launch_cholqr_split(int64_t n, int ell, const double* y64, double* q6
   if (n < (int64_t)kQrSplitMinChunks * kQrCh)
     return launch_cholqr(1, n, ell, y64, q64, q_out, out_is_double, nullptr, nullptr, status, st);
   const int nblk = (int)((n + kQrCh - 1) / kQrCh);
-  hipLaunchKernelGGL(qr_split_gram_kernel<false>, dim3(nblk), dim3(kQrThreads), 0, st, y64, nullptr, n, ell, ws);
-  hipLaunchKernelGGL(qr_split_elim_kernel, dim3(1), dim3(kQrThreads), 0, st, n, ell, ws);
-  hipLaunchKernelGGL(qr_split_gram_kernel<true>, dim3(nblk), dim3(kQrThreads), 0, st, y64, q64, n, ell, ws);
-  hipLaunchKernelGGL(qr_split_elim_kernel, dim3(1), dim3(kQrThreads), 0, st, n, ell, ws);
-  hipLaunchKernelGGL(qr_split_final_kernel, dim3(nblk), dim3(kQrThreads), 0, st, y64, q64, q64, n, ell, q_out,
-                     out_is_double, ws, status);
+  hipLaunchKernelGGL(qr_split_gram_kernel, dim3(nblk), dim3(kQrThreads), 0, st, y64, n, ell, ws);
+  // q_out is written by the final pass, or by a fallback in either pass
+  hipLaunchKernelGGL(qr_split_pass_kernel<false>, dim3(nblk), dim3(kQrThreads), 0, st, y64, y64, q64, n, ell,
+                     q_out, out_is_double, ws, 0, status);
+  hipLaunchKernelGGL(qr_split_pass_kernel<true>, dim3(nblk), dim3(kQrThreads), 0, st, y64, q64, q64, n, ell, q_out,
+                     out_is_double, ws, 1, status);
   return hipGetLastError();
 }
 

@@ -29,9 +29,22 @@ __global__ void mode_gram_kernel(const double* __restrict__ g, int64_t P, int l,
   const int a = pair - b * (b + 1) / 2;
   double s = 0.0;
   const int64_t total = P * Q;
-  for (int64_t e = threadIdx.x; e < total; e += blockDim.x) {
-    const int64_t p = e % P, q = e / P;
-    s += g[p + P * (a + (int64_t)l * q)] * g[p + P * (b + (int64_t)l * q)];
+  // eight (p, q) positions per thread and batch, their loads in flight together
+  for (int64_t e0 = threadIdx.x; e0 < total; e0 += 8 * (int64_t)blockDim.x) {
+    double x[8], y[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int64_t e = e0 + u * (int64_t)blockDim.x;
+      x[u] = 0.0;
+      y[u] = 0.0;
+      if (e < total) {
+        const int64_t q = e / P, p = e - q * P;
+        x[u] = g[p + P * (a + (int64_t)l * q)];
+        y[u] = g[p + P * (b + (int64_t)l * q)];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) s += x[u] * y[u];
   }
   s = wave_sum(s);
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
@@ -137,19 +150,34 @@ __global__ __launch_bounds__(kEigThreads) void jacobi_eig_kernel(int ell, int r,
   __syncthreads();
   int cur = 0;
   if (v_init) {
-    // T = A_in V0 into A[1], then A[0] = V0^T T
+    // Dot product of two rows (16-byte aligned, np even): pairs of entries per
+    // load, four independent partial sums.
+    auto row_dot = [&](const double* x, const double* y) {
+      double s4[4] = {0.0, 0.0, 0.0, 0.0};
+      for (int k0 = 0; k0 < np; k0 += 8) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int k = k0 + 2 * u;
+          if (k < np) {
+            const double2 a = *reinterpret_cast<const double2*>(x + k);
+            const double2 c = *reinterpret_cast<const double2*>(y + k);
+            s4[u] = fma(a.x, c.x, s4[u]);
+            s4[u] = fma(a.y, c.y, s4[u]);
+          }
+        }
+      }
+      return (s4[0] + s4[1]) + (s4[2] + s4[3]);
+    };
+    // T = A_in V0, stored transposed in A[1] (row j = column j of T), then
+    // A[0] = V0^T T: both products read rows of their operands.
     for (int e = tid; e < np * np; e += kEigThreads) {
       const int i = e % np, j = e / np;
-      double s = 0.0;
-      for (int k = 0; k < np; ++k) s += A[0][i * P + k] * VT[0][j * P + k];
-      A[1][i * P + j] = s;
+      A[1][j * P + i] = row_dot(&A[0][i * P], &VT[0][j * P]);
     }
     __syncthreads();
     for (int e = tid; e < np * np; e += kEigThreads) {
       const int i = e % np, j = e / np;
-      double s = 0.0;
-      for (int k = 0; k < np; ++k) s += VT[0][i * P + k] * A[1][k * P + j];
-      A[0][i * P + j] = s;
+      A[0][i * P + j] = row_dot(&VT[0][i * P], &A[1][j * P]);
     }
     __syncthreads();
   }
@@ -297,7 +325,17 @@ __global__ void small_gemm_kernel(const double* __restrict__ q, int64_t n, int l
   const int64_t i = idx % n;
   const int j = (int)(idx / n);
   double s = 0.0;
-  for (int k = 0; k < l; ++k) s += q[i + n * k] * w[k + (int64_t)l * j];
+  for (int k0 = 0; k0 < l; k0 += 8) {
+    double x[8], y[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int k = k0 + u;
+      x[u] = k < l ? q[i + n * k] : 0.0;
+      y[u] = k < l ? w[k + (int64_t)l * j] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) s += x[u] * y[u];
+  }
   if (out64) out64[idx] = s;
   if (out_s) {
     if (out_double)
