@@ -106,8 +106,11 @@ __global__ __launch_bounds__(512) void sketch_kernel(SketchArgs a) {
     }
   }
 
-  AccT* part = reinterpret_cast<AccT*>(a.partial) +
-               ((int64_t)blockIdx.z * a.nparts + (int64_t)kg * a.wo + w_o) * a.n_rows * CP;
+  // Partial sums hold only the chunk's real columns (row stride ncz); chunks
+  // keep slots of CP columns.
+  const int ncz = min(CP, a.ell - col0);
+  AccT* part = reinterpret_cast<AccT*>(a.partial) + (int64_t)blockIdx.z * a.nparts * a.n_rows * CP +
+               ((int64_t)kg * a.wo + w_o) * a.n_rows * ncz;
   const int n = lane & 15, g = lane >> 4;
   Tin* stage = reinterpret_cast<Tin*>(smem_raw + a.stage_off) + (int64_t)wave * 32 * xpose_pitch<MT>();
   // The host sized the LDS for lds_rows table rows.  A plan that undercounts
@@ -121,7 +124,8 @@ __global__ __launch_bounds__(512) void sketch_kernel(SketchArgs a) {
         const int64_t row = a0 + 16 * m + Pol::out_row(g, r);
         if (row < a.n_rows) {
 #pragma unroll
-          for (int t = 0; t < NT; ++t) part[row * CP + 16 * t + n] = (AccT)__builtin_nan("");
+          for (int t = 0; t < NT; ++t)
+            if (16 * t + n < ncz) part[row * ncz + 16 * t + n] = (AccT)__builtin_nan("");
         }
       }
     return;
@@ -382,12 +386,14 @@ __global__ __launch_bounds__(512) void sketch_kernel(SketchArgs a) {
       const int64_t row = a0 + 16 * m + Pol::out_row(g, r);
       if (row < a.n_rows) {
 #pragma unroll
-        for (int t = 0; t < NT; ++t) part[row * CP + 16 * t + n] = acc[m][t][r];
+        for (int t = 0; t < NT; ++t)
+          if (16 * t + n < ncz) part[row * ncz + 16 * t + n] = acc[m][t][r];
       }
     }
 }
 
-// Y[a, c] = sum_p partial[z][p][a][c mod CP] (z = c / CP), summed in fp64.
+// Y[a, c] = sum_p partial[z][p][a][c mod CP] (z = c / CP; rows of a chunk
+// hold its real columns only), summed in fp64.
 // A workgroup owns kRedRows rows of one column chunk; its threads are split
 // into `tpe` groups that sum interleaved subsets of the partials, combined in
 // LDS in a fixed order, so the result does not depend on scheduling.
@@ -401,16 +407,17 @@ __global__ __launch_bounds__(kRedThreads) void sketch_reduce_kernel(
   __shared__ double red[kRedThreads];
   const int z = blockIdx.y;
   const int64_t r0 = (int64_t)blockIdx.x * kRedRows;
-  const int E = kRedRows * cp;        // elements of this block (<= 64)
+  const int cpz = min(cp, ell - z * cp);  // real columns of this chunk (the partials' row stride)
+  const int E = kRedRows * cpz;       // elements of this block (<= 64)
   const int tpe = kRedThreads / E;    // threads per element (>= 8)
   const int t = threadIdx.x;
   const int e = t % E, sub = t / E;
-  const int64_t a = r0 + e / cp;
-  const int cc = e % cp;
-  const int64_t stride = n_rows * cp;
+  const int64_t a = r0 + e / cpz;
+  const int cc = e % cpz;
+  const int64_t stride = n_rows * cpz;
   double s = 0.0;
   if (sub < tpe && a < n_rows) {
-    const AccT* p = partial + (int64_t)z * nparts * stride + a * cp + cc;
+    const AccT* p = partial + (int64_t)z * nparts * n_rows * cp + a * cpz + cc;
     double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
     int q = sub;
     for (; q + 7 * tpe < nparts; q += 8 * tpe) {
