@@ -199,8 +199,8 @@ __global__ __launch_bounds__(64 * kTtmWaves) void ttm_kernel(TtmArgs a) {
 
 // Other modes with few items (small cores): one workgroup per (q, p group)
 // and the reduction index split over the waves.  Wave w takes the 32-row
-// slices w, w + 8, ...; it stages its own slice of Q in a private LDS region
-// and keeps the loads of its next slice of G in flight while it multiplies.
+// slices w, w + 8, ...; it loads a slice's G and Q together and stages Q in
+// a private LDS region.
 // The eight partial accumulators are summed in wave order through LDS.
 template <typename Tin, int P, int MT, int NT>
 __global__ __launch_bounds__(64 * kTtmWaves) void ttm_split_kernel(TtmArgs a) {
@@ -238,24 +238,23 @@ __global__ __launch_bounds__(64 * kTtmWaves) void ttm_split_kernel(TtmArgs a) {
       }
     }
   };
-  auto step = [&](const Tin (&x)[NT][8], int s) {
+  // One slice: its loads of G and of Q are issued together (one memory
+  // latency per slice), then Q goes through the wave's LDS region.
+  auto step = [&](int s) {
+    Tin x[NT][8];
+    load_b(x, s);
     const int64_t k0 = (int64_t)s * 32;
-    // loads in batches of eight per lane, each batch before its LDS stores
-    // (a few latencies per slice instead of one per element)
-#pragma unroll 1
-    for (int u0 = 0; u0 < CQ / 2; u0 += 8) {
-      T qv[8];
+    T qv[CQ / 2];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        const int e = lane + 64 * (u0 + u);
-        const int c = e / 32, k = e % 32;
-        qv[u] = (c < a.ell && k0 + k < a.n) ? (T)a.q[(k0 + k) + a.n * c] : (T)0;
-      }
+    for (int u = 0; u < CQ / 2; ++u) {
+      const int e = lane + 64 * u;
+      const int c = e / 32, k = e % 32;
+      qv[u] = (c < a.ell && k0 + k < a.n) ? (T)a.q[(k0 + k) + a.n * c] : (T)0;
+    }
 #pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        const int e = lane + 64 * (u0 + u);
-        st[(e / 32) * kSlicePitch + e % 32] = qv[u];
-      }
+    for (int u = 0; u < CQ / 2; ++u) {
+      const int e = lane + 64 * u;
+      st[(e / 32) * kSlicePitch + e % 32] = qv[u];
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
@@ -282,18 +281,7 @@ __global__ __launch_bounds__(64 * kTtmWaves) void ttm_split_kernel(TtmArgs a) {
       for (int m = 0; m < MT; ++m) Pol::mma(acc[m][t], af[m], bfr);
     }
   };
-  Tin xa[NT][8], xb[NT][8];
-  int s = wave;
-  if (s < nslices) load_b(xa, s);
-  while (s < nslices) {
-    if (s + kTtmWaves < nslices) load_b(xb, s + kTtmWaves);
-    step(xa, s);
-    s += kTtmWaves;
-    if (s >= nslices) break;
-    if (s + kTtmWaves < nslices) load_b(xa, s + kTtmWaves);
-    step(xb, s);
-    s += kTtmWaves;
-  }
+  for (int s = wave; s < nslices; s += kTtmWaves) step(s);
 
   // sum of the eight partial accumulators, in wave order
   __syncthreads();
