@@ -20,10 +20,10 @@ constexpr int kEigMax = 64;
 
 // Gram matrix of mode `mode` of a fp64 tensor viewed as [P][l][Q]:
 // gram[a + l b] = sum_{p,q} g[p, a, q] g[p, b, q].  One block per pair a <= b.
-__global__ void mode_gram_kernel(const double* __restrict__ g, int64_t P, int l, int64_t Q,
-                                 double* __restrict__ gram) {
-  __shared__ double red[kGramThreads / 64];
-  int pair = blockIdx.x;
+// Entry pair (a <= b) of the Gram matrix of the mode unfolding of g viewed as
+// g[p, a, q] (P x l x Q): sum over p, q of g[p, a, q] g[p, b, q].
+__device__ void mode_gram_pair(const double* __restrict__ g, int64_t P, int l, int64_t Q,
+                               double* __restrict__ gram, int pair, double* red) {
   int b = 0;
   while ((b + 1) * (b + 2) / 2 <= pair) ++b;
   const int a = pair - b * (b + 1) / 2;
@@ -55,6 +55,29 @@ __global__ void mode_gram_kernel(const double* __restrict__ g, int64_t P, int l,
     gram[a + (int64_t)l * b] = t;
     gram[b + (int64_t)l * a] = t;
   }
+}
+
+__global__ void mode_gram_kernel(const double* __restrict__ g, int64_t P, int l, int64_t Q,
+                                 double* __restrict__ gram) {
+  __shared__ double red[kGramThreads / 64];
+  mode_gram_pair(g, P, l, Q, gram, blockIdx.x, red);
+}
+
+// The Gram matrices of several mode unfoldings of one tensor in one launch:
+// workgroups [first[m], first[m + 1]) take the entry pairs of mode m.
+struct GramJobs {
+  int64_t P[kMaxDims], Q[kMaxDims];
+  int l[kMaxDims];
+  double* gram[kMaxDims];
+  int first[kMaxDims + 1];
+  int n;
+};
+
+__global__ void mode_gram_multi_kernel(const double* __restrict__ g, GramJobs jobs) {
+  __shared__ double red[kGramThreads / 64];
+  int m = 0;
+  while (m + 1 < jobs.n && (int)blockIdx.x >= jobs.first[m + 1]) ++m;
+  mode_gram_pair(g, jobs.P[m], jobs.l[m], jobs.Q[m], jobs.gram[m], (int)blockIdx.x - jobs.first[m], red);
 }
 
 __device__ __forceinline__ void wave_sync() {
@@ -430,12 +453,25 @@ hipError_t launch_truncate(const TruncPlan& p, const void* core, int core_double
   // only by the discarded components, so its Jacobi iteration starts from
   // that basis and needs few sweeps.
   EigJob jobs[kMaxDims];
+  GramJobs gj{};
+  gj.n = d;
+  gj.first[0] = 0;
   for (int i = 0; i < d; ++i) {
     double* gram = reinterpret_cast<double*>(ws + p.off_gram[i]);
-    e = gram_of(g[0], i, gram);
-    if (e != hipSuccess) return e;
+    int64_t P = 1, Q = 1;
+    for (int k = 0; k < i; ++k) P *= cur[k];
+    for (int k = i + 1; k < d; ++k) Q *= cur[k];
+    const int l = (int)cur[i];
+    gj.P[i] = P;
+    gj.Q[i] = Q;
+    gj.l[i] = l;
+    gj.gram[i] = gram;
+    gj.first[i + 1] = gj.first[i] + l * (l + 1) / 2;
     jobs[i] = EigJob{gram, nullptr, reinterpret_cast<double*>(ws + p.off_v0[i]), nullptr, p.ell[i], p.ell[i]};
   }
+  hipLaunchKernelGGL(mode_gram_multi_kernel, dim3(gj.first[d]), dim3(kGramThreads), 0, st, g[0], gj);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
   e = launch_sym_eig_jobs(d, jobs, st);
   if (e != hipSuccess) return e;
   for (int s = 0; s < d; ++s) {
