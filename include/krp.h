@@ -137,8 +137,15 @@ int krp_sthosvd(const void* X, int dtype, int d, const int64_t* dims, const int3
  * (a, c) of H_b equal to h_{a+c}; H_b is (m s_b) x (n s_b) and is never formed.
  * Omega = Omega1 kr Omega2 (s_b x ell_r, n x ell_r), Psi = Psi1 kr Psi2
  * (s_b x ell_l, m x ell_l), factor ids 0..3, counter word 3 = b.
- *   s      host, batch entries >= 1;  1 <= r <= ell_r <= min(ell_l, 64);
- *          ell_l = 0 selects ceil(1.5 ell_r); ell_l <= 64; ell_r <= m s_b
+ *   s      host, batch entries >= 1;  1 <= r <= ell_r <= ell_l <= 48;
+ *          ell_l = 0 selects ceil(1.5 ell_r); ell_r <= m s_b and ell_r <= n s_b
+ *   m, n   block sizes, 1..64
+ *   limit  the correlation of an instance keeps its length-(2 s_b - 1) sequence
+ *          in 150 KiB of LDS: s_b up to about 12,700 blocks for fp32 data and
+ *          6,300 for fp64 (larger values return KRP_EINVAL)
+ *   opts->prec  must be KRP_P_FP32 for fp32 data and KRP_P_FP64 for fp64 data:
+ *          the sketch runs in the storage precision, the small dense algebra
+ *          (Cholesky, least squares, eigenvectors) in fp64
  *   h      device, sum_b (2 s_b - 1) m n elements of `dtype`
  *   U      device, sum_b m s_b r elements: U_b (m s_b) x r column-major
  *   S      device, batch * r elements (descending per instance)

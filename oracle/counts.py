@@ -40,6 +40,15 @@ def rsthosvd_krp_count(dims, ells, order=None):
     return total
 
 
+def memo_count(dims, ells):
+    """RHOSVD-KRP-MEMO: one shared factor per mode, each with max(ell) columns
+    (mode i uses the first ell_i columns).  For uniform sizes this is d n ell:
+    the d matrices of the single set the Section 5.1 text describes, one n x ell
+    factor more than the (d-1) n ell of Table 1's MEMO column."""
+    lmax = max(ells)
+    return sum(n * lmax for n in dims)
+
+
 def table1_rng(method, d, n, ell):
     """Leading-order RNG counts of Table 1 for uniform n and ell."""
     return {

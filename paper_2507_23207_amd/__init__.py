@@ -154,11 +154,14 @@ def sthosvd(x, ranks, oversample, prec="fp32", seed=2507, draw=0, truncate=False
                    graph, order, workspace, status, autotune)
 
 
-def hankel_lowrank(s, h, m, n, r, ell_r, ell_l=0, prec="fp32", seed=2507, draw=0, graph=True):
+def hankel_lowrank(s, h, m, n, r, ell_r, ell_l=0, prec="fp32", seed=2507, draw=0, graph=True,
+                   status=None):
     """Batched single-pass block-Hankel SVD (Algorithm 6); krp_hankel_lowrank.
 
     ``s``: block counts per instance; ``h``: packed Markov blocks (1-D device
-    tensor).  Returns packed (U, S, V) 1-D tensors."""
+    tensor).  ``status``: optional int32 device tensor of one element; the
+    call then does not synchronise and ORs the status bits into it.  Returns
+    packed (U, S, V) 1-D tensors."""
     torch = _torch()
     s = [int(v) for v in s]
     if not h.is_cuda or not h.is_contiguous():
@@ -166,7 +169,7 @@ def hankel_lowrank(s, h, m, n, r, ell_r, ell_l=0, prec="fp32", seed=2507, draw=0
     U = torch.empty(sum(m * v * r for v in s), dtype=h.dtype, device=h.device)
     S = torch.empty(len(s) * r, dtype=h.dtype, device=h.device)
     V = torch.empty(sum(n * v * r for v in s), dtype=h.dtype, device=h.device)
-    o, _, keep = _opts(prec, seed, draw, graph=graph)
+    o, _, keep = _opts(prec, seed, draw, graph=graph, status=status)
     rc = _capi.lib().krp_hankel_lowrank(len(s), _capi.i64_array(s), int(m), int(n),
                                         ctypes.c_void_p(h.data_ptr()), _dtype_code(h), int(r), int(ell_r),
                                         int(ell_l), ctypes.byref(o), ctypes.c_void_p(U.data_ptr()),

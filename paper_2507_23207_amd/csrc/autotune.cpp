@@ -3,7 +3,8 @@
 // On the first use of a sketch shape -- (tensor dims, sketched mode, ell,
 // arithmetic, storage type, 16-byte alignment of the input) -- the candidate
 // tilings (row tiles per wave, waves along the rows, target workgroup count)
-// are timed with HIP events on the caller's stream and the fastest is kept.
+// are timed with HIP events on the caller's stream (median of 11 launches
+// each) and the fastest is kept if it beats the default tiling by over 2%.
 // Results live in a process-wide table and in a JSON file, one entry per line:
 //   {"version": 1, "arch": "gfx950", "entries": {
 //   "<key>": {"mt": 4, "wm": 8, "wo": 1, "target_wgs": 256, "us": 123.4},
@@ -111,18 +112,23 @@ bool same_geometry(const SketchPlan& a, const SketchPlan& b) {
 
 }  // namespace
 
+bool cached_tile(const SketchProblem& pb, SketchTile* out) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  load_locked();
+  auto it = g_table.find(tune_key(pb));
+  if (it == g_table.end()) return false;
+  *out = it->second.tile;
+  return true;
+}
+
 SketchTile tuned_tile(const SketchProblem& pb, hipStream_t st) {
   const SketchTile def{};
   if (!pb.x) return def;
   hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
   if (hipStreamIsCapturing(st, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return def;
+  SketchTile hit;
+  if (cached_tile(pb, &hit)) return hit;
   const std::string key = tune_key(pb);
-  {
-    std::lock_guard<std::mutex> lk(g_tune_mu);
-    load_locked();
-    auto it = g_table.find(key);
-    if (it != g_table.end()) return it->second.tile;
-  }
   // candidate tilings with distinct geometry, partial sums within the default's
   const SketchPlan base = plan_sketch(pb, def);
   std::vector<std::pair<SketchTile, SketchPlan>> cands;
@@ -144,39 +150,48 @@ SketchTile tuned_tile(const SketchProblem& pb, hipStream_t st) {
   for (const auto& c : cands) part_max = std::max(part_max, c.second.partial_bytes);
   void* part = nullptr;
   double* y64 = nullptr;
-  hipEvent_t e0 = nullptr, e1 = nullptr;
-  SketchTile best = def;
-  double best_us = -1.0;
+  // every repetition is bracketed by its own event pair; the median is kept
+  constexpr int kReps = 11;
+  hipEvent_t ev[kReps + 1] = {};
   bool ok = hipMalloc(&part, std::max<size_t>(part_max, 256)) == hipSuccess &&
             hipMalloc(reinterpret_cast<void**>(&y64), (size_t)base.n_rows * pb.ell * sizeof(double)) ==
-                hipSuccess &&
-            hipEventCreate(&e0) == hipSuccess && hipEventCreate(&e1) == hipSuccess;
+                hipSuccess;
+  for (int i = 0; ok && i <= kReps; ++i) ok = hipEventCreate(&ev[i]) == hipSuccess;
+  std::vector<double> med(cands.size(), -1.0);
   for (size_t i = 0; ok && i < cands.size(); ++i) {
     const SketchPlan& p = cands[i].second;
-    ok = launch_sketch(pb, p, part, y64, nullptr, 0, st) == hipSuccess;  // warm-up
-    ok = ok && hipEventRecord(e0, st) == hipSuccess;
-    for (int r = 0; ok && r < 3; ++r) ok = launch_sketch(pb, p, part, y64, nullptr, 0, st) == hipSuccess;
-    ok = ok && hipEventRecord(e1, st) == hipSuccess && hipEventSynchronize(e1) == hipSuccess;
-    float ms = 0.f;
-    ok = ok && hipEventElapsedTime(&ms, e0, e1) == hipSuccess;
+    for (int w = 0; ok && w < 2; ++w) ok = launch_sketch(pb, p, part, y64, nullptr, 0, st) == hipSuccess;
+    ok = ok && hipEventRecord(ev[0], st) == hipSuccess;
+    for (int r = 0; ok && r < kReps; ++r) {
+      ok = launch_sketch(pb, p, part, y64, nullptr, 0, st) == hipSuccess &&
+           hipEventRecord(ev[r + 1], st) == hipSuccess;
+    }
+    ok = ok && hipEventSynchronize(ev[kReps]) == hipSuccess;
+    std::vector<double> t;
+    for (int r = 0; ok && r < kReps; ++r) {
+      float ms = 0.f;
+      ok = hipEventElapsedTime(&ms, ev[r], ev[r + 1]) == hipSuccess;
+      t.push_back(ms * 1000.0);
+    }
     if (ok) {
-      const double us = ms * 1000.0 / 3.0;
-      if (best_us < 0.0 || us < best_us) {
-        best_us = us;
-        best = cands[i].first;
-      }
+      std::sort(t.begin(), t.end());
+      med[i] = t[kReps / 2];
     }
   }
-  if (e0) hipEventDestroy(e0);
-  if (e1) hipEventDestroy(e1);
+  for (int i = 0; i <= kReps; ++i)
+    if (ev[i]) hipEventDestroy(ev[i]);
   if (part) hipFree(part);
   if (y64) hipFree(y64);
   (void)hipGetLastError();  // a failed candidate must not leak into the caller's error state
-  if (!ok || best_us < 0.0) return def;
+  if (!ok || med[0] < 0.0) return def;
+  // the default stays unless a candidate beats it by more than 2%
+  size_t best = 0;
+  for (size_t i = 1; i < cands.size(); ++i)
+    if (med[i] > 0.0 && med[i] < 0.98 * med[0] && med[i] < med[best]) best = i;
   std::lock_guard<std::mutex> lk(g_tune_mu);
-  g_table[key] = Entry{best, best_us};
+  g_table[key] = Entry{cands[best].first, med[best]};
   save_locked();
-  return best;
+  return cands[best].first;
 }
 
 }  // namespace krp

@@ -91,6 +91,8 @@ int krp_hankel_lowrank(int batch, const int64_t* s, int m, int n, const void* h,
   if (o.prec < KRP_P_FP64 || o.prec > KRP_P_BF16X3) return set_error(KRP_EINVAL, "unknown precision");
   const int is_double = dtype == KRP_F64;
   if (is_double && o.prec != KRP_P_FP64) return set_error(KRP_EINVAL, "fp64 data requires KRP_P_FP64");
+  if (!is_double && o.prec != KRP_P_FP32)
+    return set_error(KRP_EINVAL, "the Hankel sketch of fp32 data runs in fp32: opts->prec must be KRP_P_FP32");
   std::vector<Group> groups;
   size_t total = 0;
   rc = plan_groups(batch, s, m, n, r, ell_r, ell_l, is_double, groups, total);

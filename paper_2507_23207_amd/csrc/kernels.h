@@ -52,8 +52,13 @@ SketchPlan plan_sketch(const SketchProblem& pb, const SketchTile& tile);
 
 // The fastest tiling of this sketch shape: from the tuning table (memory, then
 // the JSON cache file), else timed now on pb.x over the candidate tilings on
-// `st` (not while `st` is capturing; the default tile is returned then).
+// `st` (median of repeated launches; a candidate replaces the default tiling
+// only when it is faster by a margin).  Never while `st` is capturing: the
+// default tile is returned then.
 SketchTile tuned_tile(const SketchProblem& pb, hipStream_t st);
+// The tuned tiling of this shape if the table (memory or cache file) holds
+// one; never launches anything.
+bool cached_tile(const SketchProblem& pb, SketchTile* out);
 
 // Launches the sketch of one mode: partial sums into `partial` (workspace of
 // plan.partial_bytes), then the deterministic reduction into y64 (fp64,
@@ -98,8 +103,7 @@ struct TtmProblem {
   int prec = 0;
   const double* q64 = nullptr;
 };
-hipError_t launch_ttm(const TtmProblem& pb, void* qbuf, hipStream_t st);
-size_t ttm_qbuf_bytes(int64_t n, int ell);
+hipError_t launch_ttm(const TtmProblem& pb, hipStream_t st);
 
 // Casts between storage types (count elements).
 hipError_t launch_cast(const void* in, int in_is_double, void* out, int out_is_double,

@@ -11,9 +11,7 @@
 // KRP weights (Omega_f slice times W[o, :]) the B fragment.  Per-workgroup
 // partial sums are reduced deterministically (fixed order, fp64) by a second
 // kernel.
-#include "device_common.h"
-#include "kernels.h"
-#include "philox.h"
+#include "sketch_kernel.h"
 
 #include <algorithm>
 
@@ -21,376 +19,10 @@ namespace krp {
 
 namespace {
 
-struct SketchArgs {
-  const void* x;
-  void* partial;
-  int64_t n_rows, s_row, n_f, s_f;
-  int64_t o_size[kMaxDims], o_stride[kMaxDims], o_period[kMaxDims];
-  int o_fid[kMaxDims];
-  int n_out;
-  int64_t o_total, o_per_wg;
-  int f_blocks, ell, nparts, wm, wo, rows_per_wg, fid_f, lds_rows;
-  int64_t stage_off;  // byte offset of the per-wave staging regions (kLoadXpose)
-  uint64_t seed, w2_base;
-};
-
-// Load modes of the X slab:
-//   kLoadScalar  one element per lane and slot (any strides);
-//   kLoadVecF    16-byte loads along the 32-wide f block (f contiguous);
-//   kLoadXpose   16-byte loads along the rows (mode 0, rows contiguous), each
-//                wave transposing its 16 MT x 32 slab through a private LDS
-//                region into the fragment layout.
-enum LoadMode : int { kLoadScalar = 0, kLoadVecF = 1, kLoadXpose = 2 };
-
-// Reduction slot -> k offset inside the 32-wide block.  With vector loads
-// along f (the block is contiguous in memory) lane group g reads 16-byte
-// pieces so that the four groups of a row cover 64 contiguous bytes per
-// instruction.
-template <typename Tin, int LM>
-__device__ __forceinline__ int kmap(int g, int j) {
-  if constexpr (LM == kLoadVecF) {
-    constexpr int V = 16 / sizeof(Tin);
-    return V * g + 4 * V * (j / V) + (j % V);
-  } else {
-    return 8 * g + j;
-  }
-}
-
-// Pitch (elements) of a wave's transposed staging region [k][row]: 16 MT rows
-// plus 2, so that the fragment reads (16 consecutive rows at four k 8 apart)
-// fall on distinct banks and the 8-byte writes stay aligned.
-template <int MT>
-constexpr int xpose_pitch() {
-  return 16 * MT + 2;
-}
-
-template <typename Tin, int P, int LM, int MT, int NT>
-__global__ __launch_bounds__(512) void sketch_kernel(SketchArgs a) {
-  using Pol = Policy<P>;
-  using T = typename Pol::T;
-  using AccT = typename Pol::AccT;
-  constexpr int CP = 16 * NT;
-  static_assert(CP % 4 == 0, "column chunks start at multiples of four generator columns");
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  T* tab = reinterpret_cast<T*>(smem_raw);
-
-  const int lane = threadIdx.x & 63;
-  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int w_m = wave % a.wm;
-  const int w_o = wave / a.wm;
-  const int kg = blockIdx.x;
-  const int fb = kg % a.f_blocks;
-  const int64_t orange = kg / a.f_blocks;
-  const int64_t f0 = (int64_t)fb * 32;
-  const int64_t a0 = (int64_t)blockIdx.y * a.rows_per_wg + (int64_t)w_m * 16 * MT;
-  const int col0 = blockIdx.z * CP;
-  const int64_t o_begin = orange * a.o_per_wg;
-  const int64_t o_end = min(o_begin + a.o_per_wg, a.o_total);
-
-  // Rows of each outer-mode factor that this workgroup's o range touches.
-  int64_t lo[kMaxDims];
-  int toff[kMaxDims];
-  int rows_total = 32;
-#pragma unroll
-  for (int k = 0; k < kMaxDims; ++k) {
-    lo[k] = 0;
-    toff[k] = 0;
-    if (k < a.n_out) {
-      // The o range visits digits lo, lo+1, ... (cyclically, mod o_size) of
-      // this mode: at most q1 - q0 + 1 distinct values.
-      const int64_t q0 = o_begin / a.o_period[k], q1 = (o_end - 1) / a.o_period[k];
-      const int64_t cnt = min(a.o_size[k], q1 - q0 + 1);
-      lo[k] = cnt == a.o_size[k] ? 0 : q0 % a.o_size[k];
-      toff[k] = rows_total;
-      rows_total += (int)cnt;
-    }
-  }
-
-  // Partial sums hold only the chunk's real columns (row stride ncz); chunks
-  // keep slots of CP columns.
-  const int ncz = min(CP, a.ell - col0);
-  AccT* part = reinterpret_cast<AccT*>(a.partial) + (int64_t)blockIdx.z * a.nparts * a.n_rows * CP +
-               ((int64_t)kg * a.wo + w_o) * a.n_rows * ncz;
-  const int n = lane & 15, g = lane >> 4;
-  Tin* stage = reinterpret_cast<Tin*>(smem_raw + a.stage_off) + (int64_t)wave * 32 * xpose_pitch<MT>();
-  // The host sized the LDS for lds_rows table rows.  A plan that undercounts
-  // would be a planner bug: the workgroup then poisons its partial sums with
-  // NaN (reported as non-finite by the QR) instead of overrunning the LDS.
-  if (rows_total > a.lds_rows) {
-#pragma unroll
-    for (int m = 0; m < MT; ++m)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int64_t row = a0 + 16 * m + Pol::out_row(g, r);
-        if (row < a.n_rows) {
-#pragma unroll
-          for (int t = 0; t < NT; ++t)
-            if (16 * t + n < ncz) part[row * ncz + 16 * t + n] = (AccT)__builtin_nan("");
-        }
-      }
-    return;
-  }
-
-
-  typename Pol::Acc acc[MT][NT];
-#pragma unroll
-  for (int m = 0; m < MT; ++m)
-#pragma unroll
-    for (int t = 0; t < NT; ++t) acc[m][t] = Pol::zero();
-
-  const Tin* X = reinterpret_cast<const Tin*>(a.x);
-  // Outer index o as an odometer (digits, element offset, table rows): the
-  // wave starts at o_begin + w_o and advances by wo.  All uniform (SGPRs).
-  struct Odo {
-    int64_t o, off;
-    int64_t dig[kMaxDims];
-  };
-  auto odo_init = [&](int64_t o) {
-    Odo z;
-    z.o = o;
-    z.off = 0;
-    int64_t rem = o;
-#pragma unroll
-    for (int k = 0; k < kMaxDims; ++k) {
-      z.dig[k] = 0;
-      if (k < a.n_out) {
-        z.dig[k] = rem % a.o_size[k];
-        rem /= a.o_size[k];
-        z.off += z.dig[k] * a.o_stride[k];
-      }
-    }
-    return z;
-  };
-  auto odo_step = [&](Odo& z, int by) {
-    z.o += by;
-    int64_t carry = by;
-#pragma unroll
-    for (int k = 0; k < kMaxDims; ++k) {
-      if (k < a.n_out && carry != 0) {
-        int64_t dnew = z.dig[k] + carry;
-        carry = 0;
-        while (dnew >= a.o_size[k]) {
-          dnew -= a.o_size[k];
-          ++carry;
-        }
-        z.off += (dnew - z.dig[k]) * a.o_stride[k];
-        z.dig[k] = dnew;
-      }
-    }
-  };
-  // A fragments of outer step z (raw input values, converted at use).
-  auto load_a = [&](Tin (&buf)[MT][8], const Odo& z) {
-    if constexpr (LM == kLoadXpose) {
-      // rows (contiguous) in 16-byte pieces: lane = (row group rg, k offset kq)
-      constexpr int V = 16 / sizeof(Tin);
-      constexpr int RG = 16 * MT / V;       // row groups of the wave's rows
-      constexpr int KQ = 64 / RG;           // k values per instruction
-      constexpr int NL = 32 / KQ;           // loads per lane
-      const int rg = lane % RG, kq = lane / RG;
-      const int64_t row = a0 + (int64_t)V * rg;
-      const bool rv = row < a.n_rows;
-#pragma unroll
-      for (int h = 0; h < NL; ++h) {
-        const int64_t kk = f0 + kq + KQ * h;
-        Tin q[V];
-#pragma unroll
-        for (int v = 0; v < V; ++v) q[v] = (Tin)0;
-        if (rv && kk < a.n_f) {
-          const Tin* src = X + z.off + row + kk * a.s_f;
-          if constexpr (sizeof(Tin) == 4) {
-            const float4 t = *reinterpret_cast<const float4*>(src);
-            q[0] = t.x;
-            q[1] = t.y;
-            q[2] = t.z;
-            q[3] = t.w;
-          } else {
-            const double2 t = *reinterpret_cast<const double2*>(src);
-            q[0] = t.x;
-            q[1] = t.y;
-          }
-        }
-#pragma unroll
-        for (int v = 0; v < V; ++v) buf[(h * V + v) / 8][(h * V + v) % 8] = q[v];
-      }
-      return;
-    }
-#pragma unroll
-    for (int m = 0; m < MT; ++m) {
-      const int64_t row = a0 + 16 * m + n;
-      const bool rv = row < a.n_rows;
-      const int64_t base = z.off + row * a.s_row + f0 * a.s_f;
-      if constexpr (LM == kLoadVecF) {
-        if constexpr (sizeof(Tin) == 4) {
-#pragma unroll
-          for (int h = 0; h < 2; ++h) {
-            const int kk = 4 * g + 16 * h;
-            float4 q = make_float4(0.f, 0.f, 0.f, 0.f);
-            if (rv && f0 + kk < a.n_f) q = *reinterpret_cast<const float4*>(X + base + kk);
-            buf[m][4 * h + 0] = q.x;
-            buf[m][4 * h + 1] = q.y;
-            buf[m][4 * h + 2] = q.z;
-            buf[m][4 * h + 3] = q.w;
-          }
-        } else {
-#pragma unroll
-          for (int h = 0; h < 4; ++h) {
-            const int kk = 2 * g + 8 * h;
-            double2 q = make_double2(0.0, 0.0);
-            if (rv && f0 + kk < a.n_f) q = *reinterpret_cast<const double2*>(X + base + kk);
-            buf[m][2 * h + 0] = q.x;
-            buf[m][2 * h + 1] = q.y;
-          }
-        }
-      } else {
-#pragma unroll
-        for (int j = 0; j < 8; ++j) {
-          const int kk = 8 * g + j;
-          Tin v = (Tin)0;
-          if (rv && f0 + kk < a.n_f) v = X[base + (int64_t)kk * a.s_f];
-          buf[m][j] = v;
-        }
-      }
-    }
-  };
-  // Multiply the buffered slice of step z into the accumulators.
-  auto compute = [&](const Tin (&buf)[MT][8], const Odo& z) {
-    T w[NT];
-#pragma unroll
-    for (int t = 0; t < NT; ++t) w[t] = (T)1;
-#pragma unroll
-    for (int k = 0; k < kMaxDims; ++k) {
-      if (k < a.n_out) {
-        // digit and first digit both lie in [0, o_size): one wrap at most
-        int dd = (int)(z.dig[k] - lo[k]);
-        dd = dd < 0 ? dd + (int)a.o_size[k] : dd;
-        const int rr = toff[k] + dd;
-#pragma unroll
-        for (int t = 0; t < NT; ++t) w[t] = w[t] * tab[rr * CP + 16 * t + n];
-      }
-    }
-    typename Pol::Frag bf[NT];
-#pragma unroll
-    for (int t = 0; t < NT; ++t) {
-      T v[8];
-#pragma unroll
-      for (int j = 0; j < 8; ++j) v[j] = tab[kmap<Tin, LM>(g, j) * CP + 16 * t + n] * w[t];
-      bf[t] = Pol::make(v);
-    }
-    Tin xa[MT][8];
-    if constexpr (LM == kLoadXpose) {
-      // through the wave's staging region: [k][row], pitch xpose_pitch<MT>()
-      constexpr int V = 16 / sizeof(Tin);
-      constexpr int RG = 16 * MT / V;
-      constexpr int KQ = 64 / RG;
-      constexpr int NL = 32 / KQ;
-      constexpr int PT = xpose_pitch<MT>();
-      const int rg = lane % RG, kq = lane / RG;
-#pragma unroll
-      for (int h = 0; h < NL; ++h) {
-        Tin* d = stage + (kq + KQ * h) * PT + V * rg;
-#pragma unroll
-        for (int v = 0; v < V; v += 2) {
-          if constexpr (sizeof(Tin) == 4) {
-            *reinterpret_cast<float2*>(d + v) =
-                make_float2(buf[(h * V + v) / 8][(h * V + v) % 8], buf[(h * V + v + 1) / 8][(h * V + v + 1) % 8]);
-          } else {
-            *reinterpret_cast<double2*>(d + v) =
-                make_double2(buf[(h * V + v) / 8][(h * V + v) % 8], buf[(h * V + v + 1) / 8][(h * V + v + 1) % 8]);
-          }
-        }
-      }
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-      __builtin_amdgcn_wave_barrier();
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-#pragma unroll
-      for (int m = 0; m < MT; ++m)
-#pragma unroll
-        for (int j = 0; j < 8; ++j) xa[m][j] = stage[(8 * g + j) * PT + 16 * m + n];
-      // the next step's stores must not overtake these reads
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-      __builtin_amdgcn_wave_barrier();
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    } else {
-#pragma unroll
-      for (int m = 0; m < MT; ++m)
-#pragma unroll
-        for (int j = 0; j < 8; ++j) xa[m][j] = buf[m][j];
-    }
-#pragma unroll
-    for (int m = 0; m < MT; ++m) {
-      T v[8];
-#pragma unroll
-      for (int j = 0; j < 8; ++j) v[j] = (T)xa[m][j];
-      const typename Pol::Frag af = Pol::make(v);
-#pragma unroll
-      for (int t = 0; t < NT; ++t) Pol::mma(acc[m][t], af, bf[t]);
-    }
-  };
-
-  // Software pipeline: the loads of step o + wo are in flight while step o is
-  // multiplied (two register buffers, alternating).
-  Tin bufA[MT][8], bufB[MT][8];
-  Odo cur = odo_init(o_begin + w_o);
-  if (cur.o < o_end) load_a(bufA, cur);
-  // The factor table is drawn while the first slab loads are in flight.
-  // Draw the factor rows (fp64 Gaussians rounded to the working precision),
-  // four columns per generator call (the chunk start is a multiple of four),
-  // the factor and row chosen without branches; zeros in the padding.
-  const int ncol = min(CP, a.ell - col0);
-  const int nq = (ncol + 3) >> 2;
-  for (int e = threadIdx.x; e < rows_total * nq; e += blockDim.x) {
-    const int r = e / nq, jq = e - (e / nq) * nq;
-    int k = 0;
-#pragma unroll
-    for (int kk = 1; kk < kMaxDims; ++kk)
-      if (kk < a.n_out && r >= toff[kk]) k = kk;
-    const bool fr = r < 32;
-    int dd = (int)lo[k] + (r - toff[k]);
-    dd = dd >= (int)a.o_size[k] ? dd - (int)a.o_size[k] : dd;
-    const int64_t row = fr ? f0 + r : (int64_t)dd;
-    const uint64_t fid = fr ? (uint64_t)a.fid_f : (uint64_t)a.o_fid[k];
-    const bool live = !fr || row < a.n_f;
-    double g[4];
-    gauss_quad(a.seed, a.w2_base | fid, 0, row, (uint64_t)((col0 >> 2) + jq), g);
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int c = 4 * jq + u;
-      tab[r * CP + c] = (live && c < ncol) ? factor_value<P>(g[u]) : (T)0;
-    }
-  }
-  for (int e = threadIdx.x; e < rows_total * (CP - 4 * nq); e += blockDim.x) {
-    const int r = e / (CP - 4 * nq), c = 4 * nq + e % (CP - 4 * nq);
-    tab[r * CP + c] = (T)0;
-  }
-  // LDS-only barrier: the first slab loads stay in flight across it.
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
-  __builtin_amdgcn_s_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
-  while (cur.o < o_end) {
-    Odo nxt = cur;
-    odo_step(nxt, a.wo);
-    if (nxt.o < o_end) load_a(bufB, nxt);
-    compute(bufA, cur);
-    cur = nxt;
-    if (cur.o >= o_end) break;
-    odo_step(nxt, a.wo);
-    if (nxt.o < o_end) load_a(bufA, nxt);
-    compute(bufB, cur);
-    cur = nxt;
-  }
-
-#pragma unroll
-  for (int m = 0; m < MT; ++m)
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int64_t row = a0 + 16 * m + Pol::out_row(g, r);
-      if (row < a.n_rows) {
-#pragma unroll
-        for (int t = 0; t < NT; ++t)
-          if (16 * t + n < ncz) part[row * ncz + 16 * t + n] = acc[m][t][r];
-      }
-    }
-}
+using skdetail::SketchArgs;
+using skdetail::kLoadScalar;
+using skdetail::kLoadVecF;
+using skdetail::kLoadXpose;
 
 // Y[a, c] = sum_p partial[z][p][a][c mod CP] (z = c / CP; rows of a chunk
 // hold its real columns only), summed in fp64.
@@ -472,45 +104,6 @@ __global__ void gaussian_kernel(uint64_t seed, uint64_t w2, uint64_t instance, i
     reinterpret_cast<__bf16*>(out)[idx] = h;
     if (prec == kBF16X3) reinterpret_cast<__bf16*>(out)[rows * cols + idx] = (__bf16)(x - (float)h);
   }
-}
-
-template <typename Tin, int P, int LM, int MT, int NT>
-hipError_t launch_inst(const SketchArgs& args, dim3 grid, int threads, size_t lds, hipStream_t st) {
-  auto kern = sketch_kernel<Tin, P, LM, MT, NT>;
-  if (lds > 65536) {
-    hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return e;
-  }
-  hipLaunchKernelGGL(kern, grid, dim3(threads), lds, st, args);
-  return hipGetLastError();
-}
-
-template <typename Tin, int P, int LM, int MT>
-hipError_t dispatch_nt(int nt, const SketchArgs& args, dim3 grid, int threads, size_t lds, hipStream_t st) {
-  switch (nt) {
-    case 1: return launch_inst<Tin, P, LM, MT, 1>(args, grid, threads, lds, st);
-    case 2: return launch_inst<Tin, P, LM, MT, 2>(args, grid, threads, lds, st);
-    case 3: return launch_inst<Tin, P, LM, MT, 3>(args, grid, threads, lds, st);
-    default: return launch_inst<Tin, P, LM, MT, 4>(args, grid, threads, lds, st);
-  }
-}
-
-template <typename Tin, int P, int LM>
-hipError_t dispatch_mt(int mt, int nt, const SketchArgs& args, dim3 grid, int threads, size_t lds,
-                       hipStream_t st) {
-  switch (mt) {
-    case 1: return dispatch_nt<Tin, P, LM, 1>(nt, args, grid, threads, lds, st);
-    case 2: return dispatch_nt<Tin, P, LM, 2>(nt, args, grid, threads, lds, st);
-    default: return dispatch_nt<Tin, P, LM, 4>(nt, args, grid, threads, lds, st);
-  }
-}
-
-template <typename Tin, int P>
-hipError_t dispatch_lm(int lm, int mt, int nt, const SketchArgs& args, dim3 grid, int threads,
-                       size_t lds, hipStream_t st) {
-  if (lm == kLoadVecF) return dispatch_mt<Tin, P, kLoadVecF>(mt, nt, args, grid, threads, lds, st);
-  if (lm == kLoadXpose) return dispatch_mt<Tin, P, kLoadXpose>(mt, nt, args, grid, threads, lds, st);
-  return dispatch_mt<Tin, P, kLoadScalar>(mt, nt, args, grid, threads, lds, st);
 }
 
 }  // namespace
@@ -646,13 +239,13 @@ hipError_t launch_sketch(const SketchProblem& pb, const SketchPlan& p, void* par
   hipError_t e;
   if (pb.x_is_double) {
     if (pb.prec != kFP64) return hipErrorInvalidValue;
-    e = dispatch_lm<double, kFP64>(lm, p.mt, p.nt, a, grid, threads, lds, st);
+    e = skdetail::dispatch_fp64(true, lm, p.mt, p.nt, a, grid, threads, lds, st);
   } else {
     switch (pb.prec) {
-      case kFP64: e = dispatch_lm<float, kFP64>(lm, p.mt, p.nt, a, grid, threads, lds, st); break;
-      case kFP32: e = dispatch_lm<float, kFP32>(lm, p.mt, p.nt, a, grid, threads, lds, st); break;
-      case kBF16: e = dispatch_lm<float, kBF16>(lm, p.mt, p.nt, a, grid, threads, lds, st); break;
-      default: e = dispatch_lm<float, kBF16X3>(lm, p.mt, p.nt, a, grid, threads, lds, st); break;
+      case kFP64: e = skdetail::dispatch_fp64(false, lm, p.mt, p.nt, a, grid, threads, lds, st); break;
+      case kFP32: e = skdetail::dispatch_fp32(lm, p.mt, p.nt, a, grid, threads, lds, st); break;
+      case kBF16: e = skdetail::dispatch_bf16(lm, p.mt, p.nt, a, grid, threads, lds, st); break;
+      default: e = skdetail::dispatch_bf16x3(lm, p.mt, p.nt, a, grid, threads, lds, st); break;
     }
   }
   if (e != hipSuccess) return e;

@@ -1,0 +1,13 @@
+// Instantiations of the KRP sketch kernel for one arithmetic policy.
+#include "sketch_kernel.h"
+
+namespace krp {
+namespace skdetail {
+
+hipError_t dispatch_bf16x3(int lm, int mt, int nt, const SketchArgs& args, dim3 grid, int threads,
+                           size_t lds, hipStream_t st) {
+  return dispatch_lm<float, kBF16X3>(lm, mt, nt, args, grid, threads, lds, st);
+}
+
+}  // namespace skdetail
+}  // namespace krp

@@ -172,6 +172,8 @@ __global__ __launch_bounds__(kEigThreads) void jacobi_eig_kernel(int ell, int r,
   }
   __syncthreads();
   int cur = 0;
+  // position of the padding index (odd ell); every round moves it by sigma
+  int pad = (ell & 1) ? np - 1 : -1;
   if (v_init) {
     // Dot product of two rows (16-byte aligned, np even): pairs of entries per
     // load, four independent partial sums.
@@ -205,12 +207,17 @@ __global__ __launch_bounds__(kEigThreads) void jacobi_eig_kernel(int ell, int r,
     __syncthreads();
   }
   for (int sweep = 0; sweep < 60; ++sweep) {
+    // Sums over the real indices only: the padding entry of an odd ell (-1 on
+    // the diagonal, at position pad) must not set the scale of the relative
+    // stopping test.
     double off = 0.0, dia = 0.0;
     for (int e = tid; e < np * np; e += kEigThreads) {
       const int i = e % np, j = e / np;
       const double v = A[cur][i * P + j];
-      if (i != j) off += v * v;
-      else dia += v * v;
+      if (i != pad && j != pad) {
+        if (i != j) off += v * v;
+        else dia += v * v;
+      }
     }
     off = wave_sum(off);
     dia = wave_sum(dia);
@@ -305,6 +312,7 @@ __global__ __launch_bounds__(kEigThreads) void jacobi_eig_kernel(int ell, int r,
       }
       __syncthreads();
       cur ^= 1;
+      if (pad >= 0) pad = jacobi_sigma(pad, half);
     }
   }
   // descending eigenvalues by ranking (ties keep the lower position first)
@@ -500,7 +508,7 @@ hipError_t launch_truncate(const TruncPlan& p, const void* core, int core_double
     tp.q64 = wi;
     tp.out = g[(s + 1) & 1];
     tp.out_is_double = 1;
-    e = launch_ttm(tp, nullptr, st);
+    e = launch_ttm(tp, st);
     if (e != hipSuccess) return e;
     cur[i] = p.rank[i];
   }

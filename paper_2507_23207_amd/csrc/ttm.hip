@@ -395,7 +395,7 @@ hipError_t ttm_dispatch(bool mode0, bool kvec, int tiles_c, const TtmArgs& a, hi
 
 }  // namespace
 
-hipError_t launch_ttm(const TtmProblem& pb, void* /*qbuf*/, hipStream_t st) {
+hipError_t launch_ttm(const TtmProblem& pb, hipStream_t st) {
   if (pb.ell < 1 || pb.ell > 64) return hipErrorInvalidValue;
   TtmArgs a{};
   a.g = pb.g;
@@ -456,6 +456,5 @@ hipError_t launch_ttm(const TtmProblem& pb, void* /*qbuf*/, hipStream_t st) {
   }
 }
 
-size_t ttm_qbuf_bytes(int64_t, int) { return 0; }
 
 }  // namespace krp

@@ -189,8 +189,12 @@ int check(hipError_t e, const char* what) { return e == hipSuccess ? KRP_OK : hi
     if (_rc != KRP_OK) return _rc; \
   } while (0)
 
-int enqueue_tucker(const TuckerSetup& s, const krp_opts& o, const void* X, void* core,
-                   void* const* Q, char* ws, int* status, bool want_err, hipStream_t st) {
+// Enqueues the whole sweep.  With `tune` (a direct, uncaptured call), each
+// sketch's tiling is first tuned on its real input -- X or the partial core
+// the previous step left -- and the tuned plan replaces the default in `s`.
+int enqueue_tucker(TuckerSetup& s, const krp_opts& o, const void* X, void* core,
+                   void* const* Q, char* ws, int* status, bool want_err, bool tune,
+                   hipStream_t st) {
   const int d = s.d;
   const bool x64 = s.dtype == KRP_F64;
   const bool trunc = o.truncate == 1;
@@ -205,6 +209,10 @@ int enqueue_tucker(const TuckerSetup& s, const krp_opts& o, const void* X, void*
     SketchProblem pb = s.spb[step];
     pb.x = s.sthosvd ? cur : X;
     pb.x_is_double = s.sthosvd ? (cur64 ? 1 : 0) : (x64 ? 1 : 0);
+    if (tune) {
+      const SketchPlan t = plan_sketch(pb, tuned_tile(pb, st));
+      if (t.partial_bytes <= s.spl[step].partial_bytes) s.spl[step] = t;
+    }
     KRP_TRY(check(launch_sketch(pb, s.spl[step], part, y64, nullptr, 0, st), "sketch"));
     double* q64 = reinterpret_cast<double*>(ws + s.off_q64[m]);
     // the partial-sum buffer of the sketch is free again: workspace of the QR
@@ -223,7 +231,7 @@ int enqueue_tucker(const TuckerSetup& s, const krp_opts& o, const void* X, void*
       tp.q64 = q64;
       tp.out = cores[step & 1];
       tp.out_is_double = s.out64 ? 1 : 0;
-      KRP_TRY(check(launch_ttm(tp, nullptr, st), "ttm"));
+      KRP_TRY(check(launch_ttm(tp, st), "ttm"));
       cur = tp.out;
       cur64 = s.out64;
     }
@@ -243,7 +251,7 @@ int enqueue_tucker(const TuckerSetup& s, const krp_opts& o, const void* X, void*
       tp.q64 = reinterpret_cast<double*>(ws + s.off_q64[step]);
       tp.out = cores[step & 1];
       tp.out_is_double = s.out64 ? 1 : 0;
-      KRP_TRY(check(launch_ttm(tp, nullptr, st), "ttm"));
+      KRP_TRY(check(launch_ttm(tp, st), "ttm"));
       cur = tp.out;
       cur64 = s.out64;
     }
@@ -287,7 +295,7 @@ int enqueue_tucker(const TuckerSetup& s, const krp_opts& o, const void* X, void*
                      : reinterpret_cast<double*>(ws + s.off_q64[step]);
       tp.out = ws + s.off_err[step & 1];
       tp.out_is_double = 1;
-      KRP_TRY(check(launch_ttm(tp, nullptr, st), "ttm(err)"));
+      KRP_TRY(check(launch_ttm(tp, st), "ttm(err)"));
       e_cur = tp.out;
       e64 = true;
       edims[step] = r;
@@ -299,41 +307,30 @@ int enqueue_tucker(const TuckerSetup& s, const krp_opts& o, const void* X, void*
   return KRP_OK;
 }
 
-// Replaces the sketch plans by autotuned ones (their partial sums never need
-// more workspace than the default plans').  Sketches of X are timed on X; the
-// STHOSVD sketches of partial cores on a zero-filled stand-in of the core's
-// size, since their input only exists once the sweep runs.
-int autotune_tucker(TuckerSetup& s, bool sthosvd, const void* X, hipStream_t st) {
-  size_t stand_in = 0;
-  for (int step = 0; step < s.n_sketch; ++step) {
-    if (step == 0 || !sthosvd) continue;
-    const SketchProblem& pb = s.spb[step];
-    int64_t e = 1;
-    for (int k = 0; k < pb.d; ++k) e *= pb.dims[k];
-    stand_in = std::max(stand_in, (size_t)e * (pb.x_is_double ? 8 : 4));
-  }
-  void* buf = nullptr;
-  if (stand_in) {
-    hipError_t e = hipMalloc(&buf, stand_in);
-    if (e == hipSuccess) e = hipMemsetAsync(buf, 0, stand_in, st);
-    if (e != hipSuccess) {
-      if (buf) hipFree(buf);
-      return hip_fail(e, "autotune stand-in");
-    }
-  }
+// Tilings the tuning table already holds replace the default plans (only
+// when their partial sums fit the default plan's, so workspace sizes queried
+// without the flag stay valid).  Returns true when some sketch of the sweep
+// has no entry yet.  Launches nothing.
+bool apply_cached_tiles(TuckerSetup& s, const void* X, char* ws) {
+  bool missing = false;
   for (int step = 0; step < s.n_sketch; ++step) {
     SketchProblem pb = s.spb[step];
-    pb.x = (step == 0 || !sthosvd) ? X : buf;
-    const SketchTile t = tuned_tile(pb, st);
-    SketchPlan p = plan_sketch(pb, t);
+    // the input of the sketch: X, or the partial core of the previous step
+    pb.x = (step == 0 || !s.sthosvd) ? X : static_cast<const void*>(ws + s.off_core[(step - 1) & 1]);
+    SketchTile t;
+    if (!cached_tile(pb, &t)) {
+      missing = true;
+      continue;
+    }
+    const SketchPlan p = plan_sketch(pb, t);
     if (p.partial_bytes <= s.spl[step].partial_bytes) s.spl[step] = p;
   }
-  if (buf) {
-    hipError_t e = hipStreamSynchronize(st);
-    hipFree(buf);
-    if (e != hipSuccess) return hip_fail(e, "autotune");
-  }
-  return KRP_OK;
+  return missing;
+}
+
+bool stream_capturing(hipStream_t st) {
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  return hipStreamIsCapturing(st, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone;
 }
 
 int tucker_entry(bool sthosvd, const void* X, int dtype, int d, const int64_t* dims,
@@ -354,15 +351,24 @@ int tucker_entry(bool sthosvd, const void* X, int dtype, int d, const int64_t* d
   if (core_dims)
     for (int k = 0; k < d; ++k) core_dims[k] = o.truncate ? s.rank[k] : s.ell[k];
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
-  if (o.flags & KRP_FLAG_AUTOTUNE) KRP_TRY(autotune_tucker(s, sthosvd, X, st));
   char* ws = nullptr;
   KRP_TRY(acquire_workspace(&o, s.total, st, &ws));
   int* status = o.status_dev ? o.status_dev : reinterpret_cast<int*>(ws + s.off_status);
   const bool want_err = o.rel_err != nullptr;
-  const std::string key = tucker_key(s, o, X, core, Q, ws, status, want_err);
-  KRP_TRY(run_maybe_graph(key, !(o.flags & KRP_FLAG_NO_GRAPH), st, [&](hipStream_t cs) {
-    return enqueue_tucker(s, o, X, core, Q, ws, status, want_err, cs);
-  }));
+  // Autotuning: cached tilings are used as they are; a sweep with untuned
+  // sketches runs once directly (not captured), tuning each sketch on its real
+  // input.  Nothing is tuned, allocated or synchronised while the caller's
+  // stream is being captured.
+  bool tune_now = false;
+  if (o.flags & KRP_FLAG_AUTOTUNE) tune_now = apply_cached_tiles(s, X, ws) && !stream_capturing(st);
+  if (tune_now) {
+    KRP_TRY(enqueue_tucker(s, o, X, core, Q, ws, status, want_err, true, st));
+  } else {
+    const std::string key = tucker_key(s, o, X, core, Q, ws, status, want_err);
+    KRP_TRY(run_maybe_graph(key, !(o.flags & KRP_FLAG_NO_GRAPH), st, [&](hipStream_t cs) {
+      return enqueue_tucker(s, o, X, core, Q, ws, status, want_err, false, cs);
+    }));
+  }
   int rc = KRP_OK;
   if (!o.status_dev) rc = finish_status(status, st);
   if (want_err) {

@@ -125,3 +125,43 @@ def test_workspace_size_queries(L):
     assert nb.value > 0
     assert L.krp_workspace_size(5, 1, 3, dims, rank, 5, 1, ctypes.byref(nb)) == _capi.KRP_EINVAL
     assert L.krp_workspace_size(1, 0, 3, dims, rank, 5, 1, ctypes.byref(nb)) == _capi.KRP_EINVAL
+
+
+def _hankel(L, s=(10, 12), m=8, n=8, dtype=1, r=4, ell_r=8, ell_l=12, prec=None, h=FAKE):
+    o = _capi.KrpOpts()
+    L.krp_opts_default(ctypes.byref(o))
+    if prec is not None:
+        o.prec = prec
+    return L.krp_hankel_lowrank(len(s), _capi.i64_array(s), m, n, h, dtype, r, ell_r, ell_l,
+                                ctypes.byref(o), FAKE, FAKE, FAKE, None)
+
+
+@pytest.mark.parametrize("kw", [
+    dict(ell_r=40, ell_l=49),           # ell_l above the completion kernels' 48
+    dict(ell_r=40, ell_l=0),            # ceil(1.5 * 40) = 60 > 48
+    dict(m=65),                         # block rows above 64
+    dict(n=65),
+    dict(m=0),
+    dict(r=9),                          # r > ell_r
+    dict(ell_r=13, ell_l=12),           # ell_r > ell_l
+    dict(s=(0, 4)),
+    dict(s=(1, 4)),                     # replaced below: ell_r = 9 > m s = 8
+    dict(s=(20000,)),                   # the LDS-resident correlation caps s
+    dict(prec=_capi.KRP_P_BF16X3),      # the Hankel sketch runs in the storage precision
+    dict(prec=_capi.KRP_P_FP64),        # fp64 arithmetic with fp32 data
+    dict(dtype=0, prec=_capi.KRP_P_FP32),
+    dict(h=ctypes.c_void_p(0)),
+])
+def test_hankel_rejects_before_gpu(L, kw):
+    if kw.get("s") == (1, 4):
+        kw = dict(s=(1, 4), ell_r=9, ell_l=12, r=4)  # ell_r = 9 > m s = 8
+    assert _hankel(L, **kw) == _capi.KRP_EINVAL
+    assert L.krp_last_error().decode() != ""
+
+
+def test_hankel_limits_accept_the_edges(L):
+    nb = ctypes.c_size_t(0)
+    # ell_l = 48, m = n = 64 and s = 12,700 (fp32) are inside the documented limits
+    assert L.krp_hankel_workspace_size(1, _capi.i64_array((3,)), 64, 64, 4, 40, 48, ctypes.byref(nb)) == 0
+    assert L.krp_hankel_workspace_size(1, _capi.i64_array((12700,)), 8, 8, 4, 22, 33, ctypes.byref(nb)) == 0
+    assert L.krp_hankel_workspace_size(1, _capi.i64_array((3,)), 8, 8, 4, 40, 49, ctypes.byref(nb)) == 1

@@ -95,3 +95,63 @@ def test_rectangular_blocks_and_small_s():
         ref = oh.hankel_lowrank(blocks[b], r, 5, 6, seed=5, draw=2, instance=b)
         assert np.max(np.abs(sig - ref["S"])) <= 1e-9 * ref["S"][0]
         assert np.max(np.abs(u - ref["U"])) <= 1e-7
+
+
+def test_rank_deficient_sketch_takes_shifted_fallback():
+    """A series of state dimension 4 sketched with ell_r = 22: Y = H Omega has rank 4,
+    the Gram route breaks down, the shifted CholeskyQR3 fallback runs (status bit 1)
+    and the rank-4 instance is still recovered exactly."""
+    need_gpu()
+    import paper_2507_23207_amd as krp
+    m, n, r = 8, 8, 4
+    s, blocks = hankel_series(3, 20, 50, m=m, n=n, n_modes=4, noise=0.0, seed=25)
+    banner(f"hankel rank-deficient s={list(s)}")
+    hd = torch.from_numpy(pack_hankel(blocks, np.float64)).cuda()
+    status = torch.zeros(1, dtype=torch.int32, device="cuda")
+    U, S, V = krp.hankel_lowrank(list(s), hd, m, n, r, 22, 33, prec="fp64", status=status)
+    torch.cuda.synchronize()
+    st = int(status.item())
+    assert st & 1 and not st & 6, st
+    for b, (u, sig, v) in enumerate(_unpack(U, S, V, list(s), m, n, r)):
+        hm = oh.hankel_matrix(blocks[b])
+        err = np.linalg.norm(hm - u @ np.diag(sig) @ v.T) / np.linalg.norm(hm)
+        assert err <= 1e-10, (b, err)
+
+
+def test_zero_instance_reports_breakdown():
+    """An all-zero instance has no range to orthonormalise: the call reports
+    KRP_ECHOL (status bit 2) and finishes; the other instances are unaffected."""
+    need_gpu()
+    import paper_2507_23207_amd as krp
+    m, n, r = 8, 8, 12
+    s, blocks = hankel_series(3, 20, 40, m=m, n=n, n_modes=12, noise=1e-3, seed=26)
+    blocks[1] = np.zeros_like(blocks[1])
+    banner(f"hankel zero instance s={list(s)}")
+    hd = torch.from_numpy(pack_hankel(blocks, np.float64)).cuda()
+    with pytest.raises(krp.KrpError) as ei:
+        krp.hankel_lowrank(list(s), hd, m, n, r, 22, 33, prec="fp64")
+    assert ei.value.code == 4, ei.value
+    status = torch.zeros(1, dtype=torch.int32, device="cuda")
+    U, S, V = krp.hankel_lowrank(list(s), hd, m, n, r, 22, 33, prec="fp64", status=status)
+    torch.cuda.synchronize()
+    assert int(status.item()) & 2
+    res = _unpack(U, S, V, list(s), m, n, r)
+    for b in (0, 2):
+        ref = oh.hankel_lowrank(blocks[b], r, 22, 33, instance=b)
+        assert np.max(np.abs(res[b][1] - ref["S"])) <= 1e-9 * ref["S"][0], b
+
+
+@pytest.mark.parametrize("bad", [float("nan"), float("inf")])
+def test_nonfinite_series_is_reported(bad):
+    """A NaN or Inf Markov parameter returns KRP_ENONFINITE without fault."""
+    need_gpu()
+    import paper_2507_23207_amd as krp
+    m, n, r = 8, 8, 12
+    s, blocks = hankel_series(2, 30, 40, m=m, n=n, n_modes=12, noise=1e-3, seed=27)
+    blocks[0][3, 2, 5] = bad
+    banner(f"hankel non-finite {bad}")
+    for dt, prec in ((np.float64, "fp64"), (np.float32, "fp32")):
+        hd = torch.from_numpy(pack_hankel(blocks, dt)).cuda()
+        with pytest.raises(krp.KrpError) as ei:
+            krp.hankel_lowrank(list(s), hd, m, n, r, 22, 33, prec=prec)
+        assert ei.value.code == 5, ei.value

@@ -132,6 +132,56 @@ def test_oracle_draws_counted_entries(monkeypatch):
     assert sum(drawn) == counts.rsthosvd_krp_count(x.shape, [3] * 4)
 
 
+def test_memo_oracle_draws_one_shared_set_and_uses_column_prefixes(monkeypatch):
+    """RHOSVD-KRP-MEMO (Section 5.1): a single factor set (sketch id 0xFFFF), one
+    n_j x max(ell) factor per mode, and mode i sketched with the first ell_i
+    columns of every other mode's factor; the draw count against Table 1."""
+    drawn = {}
+    real = tucker.rng.factor
+
+    def spy(seed, draw, sketch, f, rows, cols, instance=0):
+        out = real(seed, draw, sketch, f, rows, cols, instance)
+        assert sketch == 0xFFFF and instance == 0
+        assert f not in drawn, "one factor per mode"
+        drawn[f] = out
+        return out
+
+    used = []
+    real_mttkrp = tucker.mttkrp
+
+    def spy_mttkrp(x, factors, mode):
+        used.append((mode, factors))
+        return real_mttkrp(x, factors, mode)
+
+    monkeypatch.setattr(tucker.rng, "factor", spy)
+    monkeypatch.setattr(tucker, "mttkrp", spy_mttkrp)
+    dims, ranks, p = (7, 6, 5, 4), (2, 3, 1, 2), 1
+    ells = [r + p for r in ranks]
+    x = low_rank_tensor(dims, (2, 2, 1, 2), noise=1e-2, seed=12)
+    g, qs = tucker.rhosvd_krp_memo(x, ranks, p, seed=5, draw=3)
+    lmax = max(ells)
+    assert sorted(drawn) == [0, 1, 2, 3]
+    for j, f in drawn.items():
+        assert f.shape == (dims[j], lmax)
+    assert [m for m, _ in used] == [0, 1, 2, 3]
+    for i, factors in used:
+        assert factors[i] is None
+        for j, f in enumerate(factors):
+            if j != i:
+                assert f.shape == (dims[j], ells[i])
+                assert np.array_equal(f, drawn[j][:, :ells[i]])
+    # the shared set differs from the fresh per-mode sets of Algorithm 7
+    fresh = real(5, 3, 0, 1, dims[1], ells[0])
+    assert not np.allclose(fresh, drawn[1][:, :ells[0]])
+    assert [q.shape for q in qs] == [(n, l) for n, l in zip(dims, ells)]
+    # counts: sum_j n_j max(ell); uniform sizes give d n ell, one n x ell factor
+    # more than the (d - 1) n ell printed in Table 1's MEMO column (a reading)
+    assert sum(f.size for f in drawn.values()) == counts.memo_count(dims, ells)
+    d, n, ell = 4, 10, 3
+    assert counts.memo_count([n] * d, [ell] * d) == counts.table1_rng("MEMO", d, n, ell) + n * ell
+    assert counts.memo_count([n] * d, [ell] * d) * (d - 1) == counts.table1_rng("RHOSVD-KRP", d, n, ell)
+
+
 def test_era_rng_percentages(golden_dir):
     import json
     import math
