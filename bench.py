@@ -1,19 +1,26 @@
 """Benchmark of the KRP sketch / randomized STHOSVD hot path on one MI355X.
 
-A step is one mixed-precision randomized STHOSVD with Khatri-Rao products
-(Algorithm 8 plus the fp64 truncation of the core) of a 512 x 512 x 512 fp32
-low-multilinear-rank tensor (rank 32, ell = 40 per mode, 1e-3 noise): for
-every mode the KRP sketch of the current core, its fp64 CholeskyQR2 and the
-TTM, all in one captured HIP graph.  The tensor is resident in HBM before
-timing starts.
+Headline workload: the 5-way 64^5 fp32 tensor (4 GiB; multilinear rank 12,
+ell = 17, core decay 0.8, noise 1e-4), resident in HBM before timing starts.
 
-Printed JSON line (one, on stdout):
-  value        algorithmic bytes of the step / step time (GB/s)
-  roofline     the single-mode KRP sketch of X (the dominant launch) timed
-               with HIP events on its stream, against 8 TB/s
-  cpu_baseline the fp64 oracle on the host cores on a sample of the step
-  plus the fp64 GPU form of the same STHOSVD, the Tucker errors of both and
-  the sketch GB/s of every mode.
+  value          GB/s of the KRP sketch of mode 1 of X (the MTTKRP of
+                 Algorithm 8, step 4: sketch kernel + its fp64 reduction, 3xBF16
+                 products on the matrix cores): algorithmic bytes (X read once,
+                 Y written once) / launch time from HIP events on its stream.
+  ms_per_step    one step = the whole hot path on that tensor: the 5-mode
+                 randomized STHOSVD with KRPs (Algorithm 8) plus the fp64
+                 truncation of the core to rank 12, one captured HIP graph.
+  sthosvd        the same step in its plain fp64 GPU form (X converted to fp64
+                 once, untimed; every stage fp64; same kernels, run through the
+                 graph as well), both Tucker errors and the time ratio.
+  roofline       the mode-1 sketch against 8 TB/s, with the HBM traffic the
+                 committed counter runs measured for it.
+  cpu_baseline   the fp64 oracle's mode-1 sketch (explicit Khatri-Rao product,
+                 unfolding, BLAS) on a sample of slabs of the same tensor.
+  workloads      the other configurations, measured the same way: the 64^3
+                 fp64 HOSVD (latency), the 512^3 STHOSVD mixed vs fp64, the
+                 128^4 HOSVD sketches (per mode and fused), the 256-instance
+                 block-Hankel batch (% of the fp32 VALU peak).
 """
 from __future__ import annotations
 
@@ -30,26 +37,26 @@ if ROOT not in sys.path:
 
 METRIC = "KRP-sketch tensor GB/s (% HBM peak); STHOSVD time mixed vs FP64 at equal error"
 HBM_PEAK_GBS = 8000.0
+FP32_VALU_PEAK_TFLOPS = 157.3
 COPY_ELEMS = 128 * 1024 * 1024  # fp32 elements of the counter-calibration copy (512 MiB)
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sketch_mode1_512x3_bf16x3_traffic.txt")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sketch_mode1_64x5_bf16x3_traffic.txt")
 # every source the sketch kernel is compiled from (the measured traffic is void once one changes)
 SKETCH_SRC = tuple(os.path.join(ROOT, "paper_2507_23207_amd", "csrc", f)
-                   for f in ("sketch.hip", "philox.h", "device_common.h", "kernels.h"))
+                   for f in ("sketch.hip", "sketch_kernel.h", "sketch_pbf16x3.hip", "philox.h",
+                             "device_common.h", "kernels.h"))
 
 
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--prec", default="bf16x3", choices=["fp32", "bf16x3", "bf16"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true", help="skip the fp64 GPU form")
-    ap.add_argument("--dims", default="512,512,512")
-    ap.add_argument("--rank", type=int, default=32)
-    ap.add_argument("--oversample", type=int, default=8)
+    ap.add_argument("--no-extras", action="store_true", help="headline workload only")
     ap.add_argument("--pmc-probe", action="store_true",
-                    help="only run a 512 MiB copy and the dominant sketch launch (for counter runs)")
+                    help="only run a 512 MiB copy and the headline sketch launch (for counter runs)")
     return ap.parse_args()
 
 
@@ -69,7 +76,7 @@ def sthosvd_bytes(dims, ells, elem):
     return total
 
 
-def time_calls(fn, steps, warmup, stream):
+def time_calls(fn, steps, warmup):
     """Wall-clock ms per call (synchronised on both sides, the step contract)."""
     import torch
     for _ in range(warmup):
@@ -83,10 +90,10 @@ def time_calls(fn, steps, warmup, stream):
 
 
 def gpu_ms(fn, reps, stream):
-    """GPU time per call from HIP events on `stream`.
-
-    A spin kernel keeps the GPU busy while the calls are enqueued, so the
-    interval between the two events holds only the calls' own kernels."""
+    """GPU time per call from HIP events recorded on `stream`, the stream the
+    library launches on.  A spin kernel keeps the GPU busy while the calls are
+    enqueued, so the interval between the two events holds only the calls'
+    own kernels."""
     import torch
     fn()
     torch.cuda.synchronize()
@@ -111,7 +118,7 @@ def source_hash(paths):
 
 
 def measured_traffic(prec):
-    """HBM bytes per launch of the dominant sketch from the committed counter
+    """HBM bytes per launch of the headline sketch from the committed counter
     runs, or None when they are missing or were taken on other kernel source."""
     try:
         kv = {}
@@ -127,62 +134,75 @@ def measured_traffic(prec):
         return None
 
 
-def cpu_baseline(x_np, ranks, p, min_seconds=10.0):
-    """The fp64 oracle (explicit KRPs, unfoldings, LAPACK) on the host cores.
+def _tensor(name, dtype=None):
+    import torch
+    from synth import WORKLOADS, low_rank_tensor_torch
+    w = WORKLOADS[name]
+    x = low_rank_tensor_torch(w["dims"], [w["rank"]] * len(w["dims"]), decay=w["decay"],
+                              noise=w["noise"], seed=w["seed"],
+                              dtype=dtype or torch.float32, device="cuda")
+    torch.cuda.synchronize()
+    return w, x
 
-    Sample: complete steps (Algorithm 8 on the full tensor, then the core
-    truncation) repeated until `min_seconds` have elapsed; the rate is the
-    step's algorithmic bytes per second, in the unit of the GPU value."""
+
+def cpu_baseline(x, ell, min_seconds=10.0):
+    """The fp64 oracle's mode-1 KRP sketch on slabs of the headline tensor.
+
+    Sample: the 64^4 slabs x[..., k] (k = 0, 1, ...), each sketched with the
+    oracle's explicit Khatri-Rao product of the four other factors, its
+    unfolding and BLAS, until `min_seconds` have elapsed.  The rate is the
+    fp32 bytes of the slabs sketched (as the GPU reads them) per second, with
+    the time split into the paper's categories (RNG, KRP formation, multiply)."""
     import numpy as np
-    from oracle import tucker as ot
+    from oracle import rng as orng
+    from oracle import tensor as otensor
 
-    x = np.asarray(x_np, dtype=np.float64)
+    d = x.dim()
     dims = list(x.shape)
-    ells = [r + p for r in ranks]
-    step_bytes = sthosvd_bytes(dims, ells, 4)
-    reps = 0
+    t_rng = t_krp = t_mul = 0.0
+    nbytes = 0
+    slabs = 0
     t0 = time.perf_counter()
-    while True:
-        g, qs = ot.rsthosvd_krp(x, ranks, p)
-        ot.truncate(g, qs, ranks)
-        reps += 1
-        dt = time.perf_counter() - t0
-        if dt >= min_seconds:
-            break
+    while time.perf_counter() - t0 < min_seconds and slabs < dims[-1]:
+        slab = x.select(d - 1, slabs).to("cpu").numpy().astype(np.float64)  # Kolda strides kept
+        a = time.perf_counter()
+        fac = [None] + [orng.factor(2507, 0, 0, k, dims[k], ell) for k in range(1, d - 1)]
+        b = time.perf_counter()
+        krp = otensor.sketch_krp(fac, 0)
+        c = time.perf_counter()
+        y = otensor.unfold(slab, 0) @ krp
+        e = time.perf_counter()
+        assert y.shape == (dims[0], ell)
+        t_rng += b - a
+        t_krp += c - b
+        t_mul += e - c
+        nbytes += slab.size * 4
+        slabs += 1
+    dt = t_rng + t_krp + t_mul
     threads = os.environ.get("OPENBLAS_NUM_THREADS") or os.environ.get("OMP_NUM_THREADS")
     cores = int(threads) if threads else (os.cpu_count() or 1)
-    return dict(value=step_bytes * reps / dt / 1e9, unit="GB/s", cores=cores, kind="oracle",
-                sample=f"{reps} full step(s) (Algorithm 8 with explicit KRPs and unfoldings, then the "
-                       f"core truncation) on the {'x'.join(map(str, dims))} tensor in fp64, "
-                       f"{dt:.1f} s", s_per_step=dt / reps)
+    return dict(value=nbytes / dt / 1e9, unit="GB/s", cores=cores, kind="oracle",
+                sample=f"mode-1 sketch of {slabs} of the {dims[-1]} slabs x[..., k] of the "
+                       f"{'x'.join(map(str, dims))} tensor (fp64 oracle, explicit KRP and unfolding), "
+                       f"{dt:.1f} s of oracle time",
+                breakdown_s={"rng": t_rng, "krp_formation": t_krp, "multiply": t_mul})
 
 
-def main():
-    args = parse()
-    if args.gpus != 1:
-        print(json.dumps({"error": "this benchmark runs on exactly one GPU; multi-GPU sharding is "
-                                   "described in DESIGN.md but not built", "n_gpus": args.gpus}))
-        sys.exit(2)
-    import numpy as np
+def headline(args, stream):
     import torch
-
     import paper_2507_23207_amd as krp
-    from synth import WORKLOADS, low_rank_tensor_torch
 
-    torch.cuda.set_device(0)
-    dims = [int(v) for v in args.dims.split(",")]
-    ranks = [args.rank] * len(dims)
-    p = args.oversample
-    ells = [r + p for r in ranks]
-    w = WORKLOADS["sthosvd_512x3_fp32"]
-    x = low_rank_tensor_torch(dims, ranks, decay=w["decay"], noise=w["noise"], seed=w["seed"],
-                              dtype=torch.float32, device="cuda")
-    torch.cuda.synchronize()
-    stream = torch.cuda.current_stream()
+    name = "sthosvd_64x5_bf16x3"
+    w, x = _tensor(name)
+    dims = list(w["dims"])
+    r, p = w["rank"], w["p"]
+    ranks = [r] * len(dims)
+    ells = [r + p] * len(dims)
+    prec = args.prec
 
     if args.pmc_probe:
         # Three plain copies of 512 MiB (the counter calibration) and three
-        # launches of the dominant sketch, nothing else; run under
+        # launches of the headline sketch, nothing else; run under
         # rocprofv3 --pmc FETCH_SIZE (then WRITE_SIZE).
         src = torch.empty(COPY_ELEMS, dtype=torch.float32, device="cuda").fill_(1.0)
         dst = torch.empty_like(src)
@@ -190,52 +210,59 @@ def main():
         for _ in range(3):
             dst.copy_(src)
         for _ in range(3):
-            krp.sketch(x, [0], [ells[0]], prec=args.prec, graph=False)
+            krp.sketch(x, [0], [ells[0]], prec=prec, graph=False)
         torch.cuda.synchronize()
         print("pmc probe done", flush=True)
-        return
+        return None
 
-    # --- the step: mixed-precision STHOSVD with truncation -------------------
-    def step():
-        return krp.sthosvd(x, ranks, p, prec=args.prec, truncate=True)
-
-    step_ms = time_calls(step, args.steps, args.warmup, stream)
-    step_gpu_ms = gpu_ms(step, args.steps, stream)
-    core, qs, err_mixed = krp.sthosvd(x, ranks, p, prec=args.prec, truncate=True, rel_err=True)
-    step_bytes = sthosvd_bytes(dims, ells, 4)
-
-    # --- dominant launch: KRP sketch of X for each mode ----------------------
+    # --- the metric: KRP sketch of mode 1 of X ------------------------------
+    reps = max(10, args.steps)
     sketch = {}
     for m in range(len(dims)):
-        fn = lambda m=m: krp.sketch(x, [m], [ells[m]], prec=args.prec)
-        ms = gpu_ms(fn, max(10, args.steps), stream)
-        b = x.numel() * 4 + dims[m] * ells[m] * 4
-        sketch[m] = dict(ms=ms, gbps=b / ms / 1e6, bytes=b)
+        fn = lambda m=m: krp.sketch(x, [m], [ells[m]], prec=prec)
+        ms = gpu_ms(fn, reps, stream)
+        nb = x.numel() * 4 + dims[m] * ells[m] * 4
+        sketch[m] = dict(ms=ms, gbps=nb / ms / 1e6, bytes=nb)
+    print(f"[bench] sketch of mode 1: {sketch[0]['ms']:.4f} ms, {sketch[0]['gbps']:.0f} GB/s",
+          file=sys.stderr, flush=True)
 
-    # --- fp64 GPU form of the same STHOSVD ------------------------------------
+    # --- the step: mixed-precision STHOSVD with truncation ---------------------
+    def step():
+        return krp.sthosvd(x, ranks, p, prec=prec, truncate=True)
+
+    step_ms = time_calls(step, args.steps, args.warmup)
+    step_gpu_ms = gpu_ms(step, args.steps, stream)
+    _, _, err_mixed = krp.sthosvd(x, ranks, p, prec=prec, truncate=True, rel_err=True)
+    step_bytes = sthosvd_bytes(dims, ells, 4)
+    print(f"[bench] sthosvd step: {step_ms:.3f} ms", file=sys.stderr, flush=True)
+
     fp64 = None
     if not args.no_fp64:
         x64 = x.to(torch.float64)  # converted once, outside the timed region
         def step64():
             return krp.sthosvd(x64, ranks, p, prec="fp64", truncate=True)
-        ms64 = time_calls(step64, max(3, args.steps // 2), 2, stream)
+        ms64 = time_calls(step64, max(3, args.steps // 2), 2)
         gms64 = gpu_ms(step64, max(3, args.steps // 2), stream)
         _, _, err64 = krp.sthosvd(x64, ranks, p, prec="fp64", truncate=True, rel_err=True)
-        fp64 = dict(ms=ms64, gpu_ms=gms64, tucker_rel_err=err64, speedup_mixed=ms64 / step_ms,
-                    speedup_mixed_gpu=gms64 / step_gpu_ms,
-                    err_ratio=err_mixed / err64)
         del x64
+        fp64 = dict(ms=ms64, gpu_ms=gms64, tucker_rel_err=err64, bytes=sthosvd_bytes(dims, ells, 8))
+        print(f"[bench] sthosvd fp64 form: {ms64:.3f} ms", file=sys.stderr, flush=True)
 
     cpu = None
     if not args.no_cpu_baseline:
-        x_np = x.permute(*reversed(range(len(dims)))).contiguous().cpu().numpy()
-        x_np = np.ascontiguousarray(x_np).transpose(*reversed(range(len(dims))))
-        cpu = cpu_baseline(x_np, ranks, p)
-
+        cpu = cpu_baseline(x, ells[0])
+    del x
     dom = sketch[0]
-    out = {
+    sth = dict(ms_mixed=step_ms, gpu_ms_mixed=step_gpu_ms, tucker_rel_err_mixed=err_mixed,
+               bytes_mixed=step_bytes, gbps_mixed=step_bytes / step_ms / 1e6)
+    if fp64:
+        sth.update(ms_fp64=fp64["ms"], gpu_ms_fp64=fp64["gpu_ms"], tucker_rel_err_fp64=fp64["tucker_rel_err"],
+                   bytes_fp64=fp64["bytes"], speedup_mixed_over_fp64=fp64["ms"] / step_ms,
+                   speedup_mixed_over_fp64_gpu=fp64["gpu_ms"] / step_gpu_ms,
+                   err_ratio_mixed_over_fp64=err_mixed / fp64["tucker_rel_err"])
+    return {
         "metric": METRIC,
-        "value": step_bytes / step_ms / 1e6,
+        "value": dom["gbps"],
         "unit": "GB/s",
         "n_gpus": 1,
         "steps": args.steps,
@@ -244,24 +271,108 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": args.prec,
+        "dtype": prec,
         "data": "synthetic",
-        "config": {"workload": "randomized STHOSVD with KRPs (Algorithm 8) + fp64 core truncation, "
-                               f"{'x'.join(map(str, dims))} fp32 tensor, multilinear rank {args.rank}, "
-                               f"ell {ells[0]}, core decay {w['decay']}, noise {w['noise']}",
-                   "dims": dims, "rank": args.rank, "ell": ells[0], "prec": args.prec,
-                   "storage": "f32", "truncate": True, "algorithmic_bytes_per_step": step_bytes},
+        "config": {"workload": "KRP sketch of mode 1 (value) and randomized STHOSVD with KRPs, Algorithm 8, "
+                               "+ fp64 truncation (step) of a 64x64x64x64x64 fp32 tensor (4 GiB), multilinear "
+                               f"rank {r}, ell {ells[0]}, core decay {w['decay']}, noise {w['noise']}, "
+                               "one captured HIP graph",
+                   "dims": dims, "rank": r, "ell": ells[0], "prec": prec, "storage": "f32",
+                   "truncate": True, "sketch_bytes": dom["bytes"], "step_bytes": step_bytes},
         "roofline": {"bound": "hbm", "achieved": dom["gbps"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": dom["gbps"] / HBM_PEAK_GBS, "traffic": measured_traffic(args.prec),
-                     "kernel": "krp_sketch of mode 1 of X (MTTKRP kernel + its reduction)",
+                     "frac": dom["gbps"] / HBM_PEAK_GBS, "traffic": measured_traffic(prec),
+                     "kernel": "krp_sketch of mode 1 of X (MTTKRP kernel + its fp64 reduction)",
                      "bytes_per_launch": dom["bytes"], "ms_per_launch": dom["ms"]},
         "cpu_baseline": cpu,
         "sketch_gbps_by_mode": [sketch[m]["gbps"] for m in range(len(dims))],
         "sketch_ms_by_mode": [sketch[m]["ms"] for m in range(len(dims))],
-        "step_gpu_ms": step_gpu_ms,
-        "tucker_rel_err_mixed": err_mixed,
-        "fp64_form": fp64,
+        "sthosvd": sth,
     }
+
+
+def extra_workloads(stream):
+    """The other configurations at a few repetitions each (the headline tensor
+    has been freed)."""
+    import numpy as np
+    import torch
+    import paper_2507_23207_amd as krp
+    from synth import WORKLOADS, hankel_series, pack_hankel
+
+    out = {}
+    # 64^3 fp64 HOSVD, paper-literal (no truncation): latency-bound, report us
+    w, x = _tensor("hosvd_64x3_fp64", torch.float64)
+    r, p = w["rank"], w["p"]
+    out["hosvd_64x3_fp64"] = dict(
+        us=1e3 * gpu_ms(lambda: krp.hosvd(x, [r] * 3, p, prec="fp64"), 50, stream),
+        note="Algorithm 7, rank 8 + 5, no truncation; latency-bound (2 MiB)")
+    del x
+    # 512^3 STHOSVD mixed vs fp64 form
+    w, x = _tensor("sthosvd_512x3_fp32")
+    r, p = w["rank"], w["p"]
+    dims = list(w["dims"])
+    ells = [r + p] * 3
+    ms = gpu_ms(lambda: krp.sthosvd(x, [r] * 3, p, prec="bf16x3", truncate=True), 10, stream)
+    _, _, e = krp.sthosvd(x, [r] * 3, p, prec="bf16x3", truncate=True, rel_err=True)
+    sk = gpu_ms(lambda: krp.sketch(x, [0], [ells[0]], prec="bf16x3"), 10, stream)
+    x64 = x.to(torch.float64)
+    del x
+    ms64 = gpu_ms(lambda: krp.sthosvd(x64, [r] * 3, p, prec="fp64", truncate=True), 5, stream)
+    _, _, e64 = krp.sthosvd(x64, [r] * 3, p, prec="fp64", truncate=True, rel_err=True)
+    del x64
+    x_bytes = math.prod(dims) * 4
+    out["sthosvd_512x3"] = dict(
+        step_ms_mixed=ms, step_ms_fp64=ms64, speedup=ms64 / ms, err_mixed=e, err_fp64=e64,
+        err_ratio=e / e64, sketch_mode1_ms=sk,
+        sketch_mode1_gbps=(x_bytes + dims[0] * ells[0] * 4) / sk / 1e6,
+        step_gbps_mixed=sthosvd_bytes(dims, ells, 4) / ms / 1e6)
+    # 128^4 HOSVD: per-mode sketches and the HOSVD with truncation
+    w, x = _tensor("hosvd_128x4_bf16x3")
+    r, p = w["rank"], w["p"]
+    dims = list(w["dims"])
+    ell = r + p
+    per = [gpu_ms(lambda m=m: krp.sketch(x, [m], [ell], prec="bf16x3"), 10, stream) for m in range(4)]
+    allm = gpu_ms(lambda: krp.sketch(x, [0, 1, 2, 3], [ell] * 4, prec="bf16x3"), 10, stream)
+    hos = gpu_ms(lambda: krp.hosvd(x, [r] * 4, p, prec="bf16x3", truncate=True), 10, stream)
+    xb = x.numel() * 4
+    out["hosvd_128x4"] = dict(
+        sketch_ms_by_mode=per, sketch_gbps_by_mode=[(xb + 128 * ell * 4) / t / 1e6 for t in per],
+        all_modes_ms=allm, all_modes_gbps_vs_one_read=(xb + 4 * 128 * ell * 4) / allm / 1e6,
+        hosvd_ms=hos)
+    del x
+    # 256-instance block-Hankel batch
+    w = WORKLOADS["hankel_256_fp32"]
+    s, blocks = hankel_series(w["batch"], w["s_lo"], w["s_hi"], m=w["m"], n=w["n"],
+                              n_modes=w["n_modes"], noise=w["noise"], seed=w["seed"])
+    m, n = w["m"], w["n"]
+    hd = torch.from_numpy(pack_hankel(blocks, np.float32)).cuda()
+    hms = gpu_ms(lambda: krp.hankel_lowrank(list(s), hd, m, n, w["r"], w["ell_r"], w["ell_l"],
+                                            prec="fp32"), 10, stream)
+    # sketch flops: Y = H Omega by the correlation (2 s^2 m ell_r) plus P_k = h_k Omega2
+    # (2 (2s - 1) m n ell_r); Z likewise with n, ell_l
+    flops = sum(2.0 * sb * sb * (m * w["ell_r"] + n * w["ell_l"])
+                + 2.0 * (2 * sb - 1) * m * n * (w["ell_r"] + w["ell_l"]) for sb in s)
+    out["hankel_256_fp32"] = dict(
+        ms=hms, sketch_gflop=flops / 1e9, tflops=flops / hms / 1e9,
+        frac_fp32_valu_peak=flops / hms / 1e9 / FP32_VALU_PEAK_TFLOPS,
+        note="whole batch (sketch, QR, completion); flops of the two sketches only")
+    return out
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this benchmark runs on exactly one GPU; multi-GPU sharding is "
+                                   "a design note, not built", "n_gpus": args.gpus}))
+        sys.exit(2)
+    import torch
+
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+    out = headline(args, stream)
+    if out is None:
+        return
+    if not args.no_extras:
+        out["workloads"] = extra_workloads(stream)
     print(json.dumps(out), flush=True)
 
 
