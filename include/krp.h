@@ -115,6 +115,23 @@ int krp_sketch(const void* X, int dtype, int d, const int64_t* dims, int nmodes,
                const int32_t* modes, const int32_t* ell, const krp_opts* opts, void* const* Y,
                void* stream);
 
+/* krp_sketch for callers that cannot allocate device memory: code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc.  Same
+ * arguments, kernels and results as krp_sketch; the partial sums live in a
+ * fixed array of the library on each GPU (krp_noalloc_scratch_bytes(), 32 MiB,
+ * held until the process ends) instead of a workspace, the kernels are
+ * launched directly on `stream` (no graph), opts->workspace, KRP_FLAG_NO_GRAPH
+ * and KRP_FLAG_AUTOTUNE are ignored, and no device memory is allocated or
+ * freed.  A sketch set whose partial sums exceed the array returns KRP_ENOMEM
+ * before any GPU work (krp_last_error() gives the size needed).  All calls on
+ * one GPU share its array: calls that overlap in time on that GPU (other
+ * streams, other threads) race and must be serialised by the caller. */
+int krp_sketch_noalloc(const void* X, int dtype, int d, const int64_t* dims, int nmodes,
+                       const int32_t* modes, const int32_t* ell, const krp_opts* opts, void* const* Y,
+                       void* stream);
+/* Bytes of the per-GPU array krp_sketch_noalloc uses. */
+size_t krp_noalloc_scratch_bytes(void);
+
 /* Randomized HOSVD with KRPs (Algorithm 7) and randomized STHOSVD with KRPs
  * (Algorithm 8).  ell_i = rank[i] + oversample, 1 <= rank[i] <= ell_i <=
  * min(dims[i], 64).  Fresh factors for every mode; in STHOSVD the factor of

@@ -20,7 +20,7 @@ from ._capi import KrpError  # noqa: F401
 PREC = {"fp64": _capi.KRP_P_FP64, "fp32": _capi.KRP_P_FP32, "bf16": _capi.KRP_P_BF16,
         "bf16x3": _capi.KRP_P_BF16X3}
 
-__all__ = ["sketch", "hosvd", "sthosvd", "hankel_lowrank", "gaussian", "kolda", "empty_kolda",
+__all__ = ["sketch", "sketch_noalloc", "hosvd", "sthosvd", "hankel_lowrank", "gaussian", "kolda", "empty_kolda",
            "workspace_size", "hankel_workspace_size", "finalize", "version", "KrpError", "PREC"]
 
 
@@ -112,6 +112,26 @@ def sketch(x, modes, ell, prec="fp32", seed=2507, draw=0, graph=True, autotune=F
                                 _capi.i64_array(x.shape), len(modes), _capi.i32_array(modes),
                                 _capi.i32_array(ell), ctypes.byref(o),
                                 _capi.ptr_array([y.data_ptr() for y in ys]), _stream(x))
+    _capi.check(rc)
+    return ys
+
+
+def sketch_noalloc(x, modes, ell, ys, prec="fp32", seed=2507, draw=0):
+    """krp_sketch_noalloc: the sketches of :func:`sketch` into the caller's
+    column-major outputs ``ys`` (one per mode), with no device allocation by
+    the library (its fixed per-GPU partial-sum array)."""
+    _check_tensor(x)
+    modes = [int(m) for m in modes]
+    ell = [int(v) for v in ell] if hasattr(ell, "__len__") else [int(ell)] * len(modes)
+    for y, m, l in zip(ys, modes, ell):
+        if (not y.is_cuda or y.dtype != x.dtype or tuple(y.shape) != (x.shape[m], l)
+                or (l > 1 and y.stride(1) != x.shape[m]) or y.stride(0) != 1):
+            raise ValueError("each Y must be a column-major (n_m, ell) tensor of x's dtype on its device")
+    o, _, keep = _opts(prec, seed, draw)
+    rc = _capi.lib().krp_sketch_noalloc(ctypes.c_void_p(x.data_ptr()), _dtype_code(x), x.dim(),
+                                        _capi.i64_array(x.shape), len(modes), _capi.i32_array(modes),
+                                        _capi.i32_array(ell), ctypes.byref(o),
+                                        _capi.ptr_array([y.data_ptr() for y in ys]), _stream(x))
     _capi.check(rc)
     return ys
 

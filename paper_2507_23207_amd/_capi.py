@@ -21,7 +21,7 @@ KRP_FLAG_NO_GRAPH, KRP_FLAG_AUTOTUNE = 1, 2
 EXPORTED = (
     "krp_opts_default", "krp_sketch", "krp_hosvd", "krp_sthosvd", "krp_hankel_lowrank",
     "krp_workspace_size", "krp_hankel_workspace_size", "krp_gaussian", "krp_status_string",
-    "krp_last_error", "krp_version", "krp_finalize",
+    "krp_last_error", "krp_version", "krp_finalize", "krp_sketch_noalloc", "krp_noalloc_scratch_bytes",
 )
 
 
@@ -66,6 +66,10 @@ def lib() -> ctypes.CDLL:
         L.krp_opts_default.restype = None
         L.krp_sketch.argtypes = [P, i, i, I64P, i, I32P, I32P, OP, ctypes.POINTER(P), P]
         L.krp_sketch.restype = i
+        L.krp_sketch_noalloc.argtypes = [P, i, i, I64P, i, I32P, I32P, OP, ctypes.POINTER(P), P]
+        L.krp_sketch_noalloc.restype = i
+        L.krp_noalloc_scratch_bytes.argtypes = []
+        L.krp_noalloc_scratch_bytes.restype = ctypes.c_size_t
         for name in ("krp_hosvd", "krp_sthosvd"):
             f = getattr(L, name)
             f.argtypes = [P, i, i, I64P, I32P, i32, OP, P, ctypes.POINTER(P), I64P, P]

@@ -7,6 +7,7 @@
 #include <string>
 
 #include "../../include/krp.h"
+#include "kernels.h"
 
 namespace krp {
 
@@ -29,6 +30,20 @@ int run_maybe_graph(const std::string& key, bool use_graph, hipStream_t st,
 int finish_status(const int* status_ws, hipStream_t st);
 
 std::string ptr_key(const void* p);
+
+// The sketches of krp_sketch: validated problems and their plans, and the
+// workspace (partial sums) they need.  `tune`: autotuned tilings.
+struct SketchSet {
+  int nmodes = 0, out_double = 0;
+  SketchProblem pb[kMaxDims];
+  SketchPlan pl[kMaxDims];
+  size_t ws_bytes = 0;
+};
+int prepare_sketches(const void* X, int dtype, int d, const int64_t* dims, int nmodes,
+                     const int32_t* modes, const int32_t* ell, void* const* Y, const krp_opts& o,
+                     bool tune, hipStream_t st, SketchSet* out);
+// Enqueues the sketches on `st` with `ws` (ss.ws_bytes) as partial-sum buffer.
+int enqueue_sketches(const SketchSet& ss, char* ws, void* const* Y, hipStream_t st);
 int release_all();
 
 inline size_t align_up(size_t v, size_t a = 256) { return (v + a - 1) / a * a; }

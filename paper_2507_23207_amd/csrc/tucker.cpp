@@ -383,6 +383,51 @@ int tucker_entry(bool sthosvd, const void* X, int dtype, int d, const int64_t* d
 
 }  // namespace
 
+int prepare_sketches(const void* X, int dtype, int d, const int64_t* dims, int nmodes,
+                     const int32_t* modes, const int32_t* ell, void* const* Y, const krp_opts& o,
+                     bool tune, hipStream_t st, SketchSet* out) {
+  KRP_TRY(validate_tensor(X, dtype, d, dims, o.prec));
+  if (nmodes < 1 || nmodes > d) return set_error(KRP_EINVAL, "nmodes=%d outside 1..d", nmodes);
+  if (!modes || !ell || !Y) return set_error(KRP_EINVAL, "modes, ell and Y must not be NULL");
+  bool seen[kMaxDims] = {false};
+  SketchSet& ss = *out;
+  ss.nmodes = nmodes;
+  ss.out_double = dtype == KRP_F64 ? 1 : 0;
+  size_t part = 0;
+  for (int j = 0; j < nmodes; ++j) {
+    const int m = modes[j];
+    if (m < 0 || m >= d || seen[m]) return set_error(KRP_EINVAL, "modes must be distinct values in 0..d-1");
+    seen[m] = true;
+    if (ell[j] < 1 || ell[j] > kMaxEll) return set_error(KRP_EINVAL, "ell[%d]=%d outside 1..64", j, ell[j]);
+    if (!Y[j]) return set_error(KRP_EINVAL, "Y[%d] is NULL", j);
+    SketchProblem& pb = ss.pb[j];
+    pb.x = X;
+    pb.x_is_double = dtype == KRP_F64;
+    pb.d = d;
+    for (int k = 0; k < d; ++k) pb.dims[k] = dims[k];
+    pb.mode = m;
+    pb.ell = ell[j];
+    pb.prec = o.prec;
+    pb.seed = o.seed;
+    pb.draw = o.draw;
+    pb.sketch_id = (uint32_t)m;
+    ss.pl[j] = plan_sketch(pb, SketchTile{});
+    if (tune) {
+      const SketchPlan t = plan_sketch(pb, tuned_tile(pb, st));
+      if (t.partial_bytes <= ss.pl[j].partial_bytes) ss.pl[j] = t;
+    }
+    part = std::max(part, ss.pl[j].partial_bytes);
+  }
+  ss.ws_bytes = align_up(part);
+  return KRP_OK;
+}
+
+int enqueue_sketches(const SketchSet& ss, char* ws, void* const* Y, hipStream_t st) {
+  for (int j = 0; j < ss.nmodes; ++j)
+    KRP_TRY(check(launch_sketch(ss.pb[j], ss.pl[j], ws, nullptr, Y[j], ss.out_double, st), "sketch"));
+  return KRP_OK;
+}
+
 }  // namespace krp
 
 using namespace krp;
@@ -396,53 +441,21 @@ int krp_sketch(const void* X, int dtype, int d, const int64_t* dims, int nmodes,
     o = *opts;
   else
     krp_opts_default(&o);
-  KRP_TRY(validate_tensor(X, dtype, d, dims, o.prec));
-  if (nmodes < 1 || nmodes > d) return set_error(KRP_EINVAL, "nmodes=%d outside 1..d", nmodes);
-  if (!modes || !ell || !Y) return set_error(KRP_EINVAL, "modes, ell and Y must not be NULL");
-  bool seen[kMaxDims] = {false};
-  SketchProblem pbs[kMaxDims];
-  SketchPlan pls[kMaxDims];
-  size_t part = 0;
-  for (int j = 0; j < nmodes; ++j) {
-    const int m = modes[j];
-    if (m < 0 || m >= d || seen[m]) return set_error(KRP_EINVAL, "modes must be distinct values in 0..d-1");
-    seen[m] = true;
-    if (ell[j] < 1 || ell[j] > kMaxEll) return set_error(KRP_EINVAL, "ell[%d]=%d outside 1..64", j, ell[j]);
-    if (!Y[j]) return set_error(KRP_EINVAL, "Y[%d] is NULL", j);
-    SketchProblem& pb = pbs[j];
-    pb.x = X;
-    pb.x_is_double = dtype == KRP_F64;
-    pb.d = d;
-    for (int k = 0; k < d; ++k) pb.dims[k] = dims[k];
-    pb.mode = m;
-    pb.ell = ell[j];
-    pb.prec = o.prec;
-    pb.seed = o.seed;
-    pb.draw = o.draw;
-    pb.sketch_id = (uint32_t)m;
-    pls[j] = plan_sketch(pb, SketchTile{});
-    if (o.flags & KRP_FLAG_AUTOTUNE) {
-      const SketchPlan t = plan_sketch(pb, tuned_tile(pb, reinterpret_cast<hipStream_t>(stream)));
-      if (t.partial_bytes <= pls[j].partial_bytes) pls[j] = t;
-    }
-    part = std::max(part, pls[j].partial_bytes);
-  }
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  SketchSet ss;
+  KRP_TRY(prepare_sketches(X, dtype, d, dims, nmodes, modes, ell, Y, o, (o.flags & KRP_FLAG_AUTOTUNE) != 0,
+                           st, &ss));
   char* ws = nullptr;
-  KRP_TRY(acquire_workspace(&o, align_up(part), st, &ws));
+  KRP_TRY(acquire_workspace(&o, ss.ws_bytes, st, &ws));
   std::string key = "sketch|dt=" + std::to_string(dtype) + "|p=" + std::to_string(o.prec) +
                     "|seed=" + std::to_string(o.seed) + "|draw=" + std::to_string(o.draw) +
                     "|X=" + ptr_key(X) + "|ws=" + ptr_key(ws) + "|";
   for (int k = 0; k < d; ++k) key += std::to_string(dims[k]) + ",";
   for (int j = 0; j < nmodes; ++j)
     key += "|" + std::to_string(modes[j]) + "," + std::to_string(ell[j]) + "," + ptr_key(Y[j]) + ",t=" +
-           plan_key(pls[j]);
-  return run_maybe_graph(key, !(o.flags & KRP_FLAG_NO_GRAPH), st, [&](hipStream_t cs) -> int {
-    for (int j = 0; j < nmodes; ++j) {
-      KRP_TRY(check(launch_sketch(pbs[j], pls[j], ws, nullptr, Y[j], dtype == KRP_F64, cs), "sketch"));
-    }
-    return KRP_OK;
-  });
+           plan_key(ss.pl[j]);
+  return run_maybe_graph(key, !(o.flags & KRP_FLAG_NO_GRAPH), st,
+                         [&](hipStream_t cs) -> int { return enqueue_sketches(ss, ws, Y, cs); });
 }
 
 int krp_hosvd(const void* X, int dtype, int d, const int64_t* dims, const int32_t* rank,

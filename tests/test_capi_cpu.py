@@ -165,3 +165,35 @@ def test_hankel_limits_accept_the_edges(L):
     assert L.krp_hankel_workspace_size(1, _capi.i64_array((3,)), 64, 64, 4, 40, 48, ctypes.byref(nb)) == 0
     assert L.krp_hankel_workspace_size(1, _capi.i64_array((12700,)), 8, 8, 4, 22, 33, ctypes.byref(nb)) == 0
     assert L.krp_hankel_workspace_size(1, _capi.i64_array((3,)), 8, 8, 4, 40, 49, ctypes.byref(nb)) == 1
+
+
+@pytest.mark.parametrize("kw", [
+    dict(X=ctypes.c_void_p(0)),
+    dict(dims=(8, 0, 8)),
+    dict(modes=(3,)),
+    dict(ell=(65,)),
+    dict(Y=(ctypes.c_void_p(0),)),
+])
+def test_sketch_noalloc_rejects_before_gpu(L, kw):
+    """The allocation-free entry point validates like krp_sketch, before any HIP call."""
+    o = _capi.KrpOpts()
+    L.krp_opts_default(ctypes.byref(o))
+    a = dict(X=FAKE, dtype=1, dims=(8, 8, 8), modes=(0,), ell=(4,), Y=(FAKE,))
+    a.update(kw)
+    rc = L.krp_sketch_noalloc(a["X"], a["dtype"], len(a["dims"]), _capi.i64_array(a["dims"]), len(a["modes"]),
+                              _capi.i32_array(a["modes"]), _capi.i32_array(a["ell"]), ctypes.byref(o),
+                              _capi.ptr_array([y.value for y in a["Y"]]), None)
+    assert rc == _capi.KRP_EINVAL
+    assert L.krp_last_error().decode() != ""
+
+
+def test_sketch_noalloc_rejects_sketches_beyond_its_array(L):
+    """Partial sums larger than the fixed per-GPU array: KRP_ENOMEM, with the size, before any HIP call."""
+    assert L.krp_noalloc_scratch_bytes() == 32 << 20
+    o = _capi.KrpOpts()
+    L.krp_opts_default(ctypes.byref(o))
+    dims = (4096, 4096, 512)  # mode-1 sketch, ell 64: far more partial sums than 32 MiB
+    rc = L.krp_sketch_noalloc(FAKE, 1, 3, _capi.i64_array(dims), 1, _capi.i32_array((0,)),
+                              _capi.i32_array((64,)), ctypes.byref(o), _capi.ptr_array([FAKE.value]), None)
+    assert rc == _capi.KRP_ENOMEM
+    assert "partial sums" in L.krp_last_error().decode()
