@@ -15,6 +15,7 @@ struct SketchTile {
   int wo = 0;         // waves splitting the outer iterations (0: derived)
   int64_t o_per_wg = 0;  // outer iterations per workgroup (0: derived)
   int target_wgs = 256;  // workgroups aimed for when deriving o_per_wg
+  int waves = 8;         // waves per workgroup (wm * wo <= waves)
 };
 
 // Problem description of a single-mode MTTKRP sketch
@@ -40,12 +41,13 @@ struct SketchPlan {
   int o_fid[kMaxDims];
   int64_t o_total, o_per_wg;
   int o_ranges, f_blocks, row_blocks, col_chunks;
-  int mt, nt, wm, wo, kvec, xpose;
-  size_t stage_bytes;     // per-wave transposition staging (mode 0), all waves
-  int cpad, nparts;
+  int mt, nt, wm, wo, kvec, rowvec;
+  int cpad, nparts;       // nparts: one partial per workgroup (f block, o range)
+  int nseg;               // level-1 segments of the reduction (1: single level)
   int lds_rows;           // factor-table rows the LDS allocation holds
   size_t lds_bytes;
-  size_t partial_bytes;   // bytes of the partial-sum buffer
+  size_t lvl_off;         // byte offset of the level-1 sums (nseg > 1)
+  size_t partial_bytes;   // bytes of the partial-sum buffer (and level-1 sums)
 };
 
 SketchPlan plan_sketch(const SketchProblem& pb, const SketchTile& tile);

@@ -22,70 +22,98 @@ namespace {
 using skdetail::SketchArgs;
 using skdetail::kLoadScalar;
 using skdetail::kLoadVecF;
-using skdetail::kLoadXpose;
+using skdetail::kLoadRowVec;
 
-// Y[a, c] = sum_p partial[z][p][a][c mod CP] (z = c / CP; rows of a chunk
-// hold its real columns only), summed in fp64.
-// A workgroup owns kRedRows rows of one column chunk; its threads are split
-// into `tpe` groups that sum interleaved subsets of the partials, combined in
-// LDS in a fixed order, so the result does not depend on scheduling.
-constexpr int kRedThreads = 512;
-constexpr int kRedRows = 1;
+// Deterministic fp64 reduction of the per-workgroup partial sums.  Chunk z
+// of the columns holds nparts partials of E_z = n_rows * ncz_z values (ncz_z
+// its real columns), one after the other.  Level 1: workgroup (element block,
+// segment, chunk) sums the partials of its segment, in order, one thread per
+// element (coalesced across threads); with a single segment it writes Y
+// directly, otherwise its fp64 sums go to `lvl`, and level 2 adds the
+// segments in order.  The summation order is fixed, so the result does not
+// depend on scheduling.
+constexpr int kRedThreads = 256;
+constexpr int kRedSeg = 32;  // partials per level-1 segment
+
+__device__ __forceinline__ void store_y(int64_t e, int ncz, int64_t n_rows, int col0, double v, double* y64,
+                                        void* yout, int out_double) {
+  const int64_t a = e / ncz;
+  const int c = col0 + (int)(e - a * ncz);
+  const int64_t o = a + n_rows * c;
+  if (y64) y64[o] = v;
+  if (yout) {
+    if (out_double)
+      reinterpret_cast<double*>(yout)[o] = v;
+    else
+      reinterpret_cast<float*>(yout)[o] = (float)v;
+  }
+}
 
 template <typename AccT>
-__global__ __launch_bounds__(kRedThreads) void sketch_reduce_kernel(
-    const AccT* __restrict__ partial, int nparts, int64_t n_rows, int ell, int cp,
-    double* __restrict__ y64, void* yout, int out_double) {
-  __shared__ double red[kRedThreads];
+__global__ __launch_bounds__(kRedThreads) void sketch_reduce1_kernel(
+    const AccT* __restrict__ partial, int nparts, int64_t n_rows, int ell, int cp, double* __restrict__ lvl,
+    int nseg, double* __restrict__ y64, void* yout, int out_double) {
+  const int z = blockIdx.z;
+  const int ncz = min(cp, ell - z * cp);
+  const int64_t E = n_rows * ncz;
+  const int64_t e = (int64_t)blockIdx.x * kRedThreads + threadIdx.x;
+  if (e >= E) return;
+  const int seg = blockIdx.y;
+  const int p0 = seg * kRedSeg, p1 = min(nparts, p0 + kRedSeg);
+  const AccT* src = partial + (int64_t)z * nparts * n_rows * cp + e;
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+  int q = p0;
+  for (; q + 7 < p1; q += 8) {
+    double v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = (double)src[(int64_t)(q + u) * E];
+    s0 += v[0] + v[4];
+    s1 += v[1] + v[5];
+    s2 += v[2] + v[6];
+    s3 += v[3] + v[7];
+  }
+  for (; q < p1; ++q) s0 += (double)src[(int64_t)q * E];
+  const double s = (s0 + s1) + (s2 + s3);
+  if (nseg == 1)
+    store_y(e, ncz, n_rows, z * cp, s, y64, yout, out_double);
+  else
+    lvl[((int64_t)z * nseg + seg) * n_rows * cp + e] = s;
+}
+
+// Level 2: a workgroup owns 64 elements; its four thread groups sum
+// consecutive quarters of the segments, and the quarters are added in order.
+__global__ __launch_bounds__(kRedThreads) void sketch_reduce2_kernel(const double* __restrict__ lvl, int nseg,
+                                                                     int64_t n_rows, int ell, int cp,
+                                                                     double* __restrict__ y64, void* yout,
+                                                                     int out_double) {
+  __shared__ double part[kRedThreads];
   const int z = blockIdx.y;
-  const int64_t r0 = (int64_t)blockIdx.x * kRedRows;
-  const int cpz = min(cp, ell - z * cp);  // real columns of this chunk (the partials' row stride)
-  const int E = kRedRows * cpz;       // elements of this block (<= 64)
-  const int tpe = kRedThreads / E;    // threads per element (>= 8)
-  const int t = threadIdx.x;
-  const int e = t % E, sub = t / E;
-  const int64_t a = r0 + e / cpz;
-  const int cc = e % cpz;
-  const int64_t stride = n_rows * cpz;
+  const int ncz = min(cp, ell - z * cp);
+  const int64_t E = n_rows * ncz;
+  const int el = threadIdx.x & 63, grp = threadIdx.x >> 6;
+  const int64_t e = (int64_t)blockIdx.x * 64 + el;
+  const int per = (nseg + 3) / 4;
+  const int q0 = grp * per, q1 = min(nseg, q0 + per);
   double s = 0.0;
-  if (sub < tpe && a < n_rows) {
-    const AccT* p = partial + (int64_t)z * nparts * n_rows * cp + a * cpz + cc;
+  if (e < E) {
+    const double* src = lvl + (int64_t)z * nseg * n_rows * cp + e;
+    const int64_t st = n_rows * cp;
     double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-    int q = sub;
-    for (; q + 7 * tpe < nparts; q += 8 * tpe) {
-      const double v0 = (double)p[(int64_t)q * stride];
-      const double v1 = (double)p[(int64_t)(q + tpe) * stride];
-      const double v2 = (double)p[(int64_t)(q + 2 * tpe) * stride];
-      const double v3 = (double)p[(int64_t)(q + 3 * tpe) * stride];
-      const double v4 = (double)p[(int64_t)(q + 4 * tpe) * stride];
-      const double v5 = (double)p[(int64_t)(q + 5 * tpe) * stride];
-      const double v6 = (double)p[(int64_t)(q + 6 * tpe) * stride];
-      const double v7 = (double)p[(int64_t)(q + 7 * tpe) * stride];
-      s0 += v0 + v4;
-      s1 += v1 + v5;
-      s2 += v2 + v6;
-      s3 += v3 + v7;
+    int q = q0;
+    for (; q + 3 < q1; q += 4) {
+      s0 += src[(int64_t)q * st];
+      s1 += src[(int64_t)(q + 1) * st];
+      s2 += src[(int64_t)(q + 2) * st];
+      s3 += src[(int64_t)(q + 3) * st];
     }
-    for (; q < nparts; q += tpe) s0 += (double)p[(int64_t)q * stride];
+    for (; q < q1; ++q) s0 += src[(int64_t)q * st];
     s = (s0 + s1) + (s2 + s3);
   }
-  red[t] = s;
+  part[threadIdx.x] = s;
   __syncthreads();
-  if (sub == 0 && a < n_rows) {
-    double tot = red[e];
-    for (int k = 1; k < tpe; ++k) tot += red[e + k * E];
-    const int c = z * cp + cc;
-    if (c < ell) {
-      const int64_t o = a + n_rows * c;
-      if (y64) y64[o] = tot;
-      if (yout) {
-        if (out_double)
-          reinterpret_cast<double*>(yout)[o] = tot;
-        else
-          reinterpret_cast<float*>(yout)[o] = (float)tot;
-      }
-    }
-  }
+  if (grp == 0 && e < E)
+    store_y(e, ncz, n_rows, z * cp, ((part[el] + part[64 + el]) + part[128 + el]) + part[192 + el], y64, yout,
+            out_double);
 }
 
 __global__ void gaussian_kernel(uint64_t seed, uint64_t w2, uint64_t instance, int64_t rows,
@@ -142,22 +170,26 @@ SketchPlan plan_sketch(const SketchProblem& pb, const SketchTile& tile) {
   int mt = tile.mt;
   if (mt != 1 && mt != 2) mt = 4;
   while (mt > 1 && 16 * (mt / 2) >= p.n_rows) mt /= 2;
-  // Mode 0 reads rows along the contiguous index.  Scalar (strided) loads
-  // need one 64-bit address per element: keep the register budget within two
-  // waves per SIMD by halving the row tiles.  The staged 16-byte path
-  // (fp32 storage, 16-byte aligned data, n_0 a multiple of 4) keeps 64 rows.
-  const int64_t vlen = 16 / (pb.x_is_double ? 8 : 4);
-  const bool x_aligned = (reinterpret_cast<uintptr_t>(pb.x) & 15) == 0;
-  p.xpose = (i == 0) && pb.d >= 2 && (p.n_rows % vlen == 0);
-  if (i == 0 && mt > 2 && !(p.xpose && x_aligned && !pb.x_is_double)) mt = 2;
+  const size_t xsz = pb.x_is_double ? 8 : 4;
+  const int64_t vlen = 16 / (int64_t)xsz;
   if (fp64 && mt > 2 && p.nt >= 3) mt = 2;  // register budget of fp64 fragments
+  // Mode 0 reads rows along the contiguous index: each lane loads mt
+  // consecutive rows as one vector (at most 16 bytes, aligned), which needs
+  // n_0 to be a multiple of mt.  Otherwise the loads are scalar (one 64-bit
+  // address per element): the row tiles are halved to keep the register
+  // budget within two waves per SIMD.
+  if (i == 0 && pb.x_is_double && mt > 2) mt = 2;
+  while (i == 0 && mt > 1 && p.n_rows % mt != 0) mt /= 2;
+  p.rowvec = (i == 0) && (reinterpret_cast<uintptr_t>(pb.x) % ((uintptr_t)mt * xsz) == 0);
+  if (i == 0 && mt > 2 && !p.rowvec) mt = 2;
   p.mt = mt;
   const int64_t wave_rows = 16 * mt;
-  int wm = tile.wm > 0 ? tile.wm : (int)std::min<int64_t>(8, (p.n_rows + wave_rows - 1) / wave_rows);
-  p.wm = std::max(1, std::min(8, wm));
+  const int wmax = std::max(1, std::min(8, tile.waves));
+  int wm = tile.wm > 0 ? tile.wm : (int)std::min<int64_t>(wmax, (p.n_rows + wave_rows - 1) / wave_rows);
+  p.wm = std::max(1, std::min(wmax, wm));
   p.row_blocks = (int)((p.n_rows + wave_rows * p.wm - 1) / (wave_rows * p.wm));
-  int wo = tile.wo > 0 ? tile.wo : std::max(1, 8 / p.wm);
-  while (p.wm * wo > 8) --wo;
+  int wo = tile.wo > 0 ? tile.wo : std::max(1, wmax / p.wm);
+  while (p.wm * wo > wmax) --wo;
   p.wo = std::max(1, wo);
   p.f_blocks = (int)((p.n_f + 31) / 32);
   p.kvec = (i != 0) && (p.n_f % vlen == 0);
@@ -187,11 +219,15 @@ SketchPlan plan_sketch(const SketchProblem& pb, const SketchTile& tile) {
     if (p.lds_bytes <= 65536 || o_per == 1) break;
     o_per = (o_per + 1) / 2;
   }
+  // the end-of-kernel wave reduction reuses the table's LDS
+  p.lds_bytes = std::max(p.lds_bytes, skdetail::wave_reduce_lds(p.wm, p.wo, p.mt, p.nt));
   p.o_per_wg = o_per;
-  p.stage_bytes = (size_t)8 * 32 * (16 * p.mt + 2) * (pb.x_is_double ? 8 : 4);  // 8 waves (upper bound)
   p.o_ranges = (int)((p.o_total + o_per - 1) / o_per);
-  p.nparts = p.f_blocks * p.o_ranges * p.wo;
+  p.nparts = p.f_blocks * p.o_ranges;  // one partial per workgroup
+  p.nseg = (p.nparts + kRedSeg - 1) / kRedSeg;
   p.partial_bytes = (size_t)p.col_chunks * p.nparts * p.n_rows * p.cpad * tsz;
+  p.lvl_off = (p.partial_bytes + 255) / 256 * 256;
+  if (p.nseg > 1) p.partial_bytes = p.lvl_off + (size_t)p.col_chunks * p.nseg * p.n_rows * p.cpad * sizeof(double);
   return p;
 }
 
@@ -226,14 +262,13 @@ hipError_t launch_sketch(const SketchProblem& pb, const SketchPlan& p, void* par
   a.seed = pb.seed;
   a.w2_base = counter_word2(pb.draw, pb.sketch_id, 0);
 
-  // Vector loads need 16-byte aligned rows; misaligned views take the scalar path.
-  const bool aligned = (reinterpret_cast<uintptr_t>(pb.x) & 15) == 0;
+  // Vector loads need aligned rows; misaligned views take the scalar path.
+  const uintptr_t xa = reinterpret_cast<uintptr_t>(pb.x);
+  const size_t xsz = pb.x_is_double ? 8 : 4;
   int lm = kLoadScalar;
-  if (aligned && p.kvec) lm = kLoadVecF;
-  if (aligned && p.xpose) lm = kLoadXpose;
-  size_t lds = p.lds_bytes;
-  a.stage_off = (int64_t)((lds + 15) / 16 * 16);
-  if (lm == kLoadXpose) lds = (size_t)a.stage_off + p.stage_bytes;
+  if ((xa & 15) == 0 && p.kvec) lm = kLoadVecF;
+  if (p.rowvec && xa % ((uintptr_t)p.mt * xsz) == 0) lm = kLoadRowVec;
+  const size_t lds = p.lds_bytes;
   const dim3 grid((unsigned)(p.f_blocks * p.o_ranges), (unsigned)p.row_blocks, (unsigned)p.col_chunks);
   const int threads = 64 * p.wm * p.wo;
   hipError_t e;
@@ -249,15 +284,25 @@ hipError_t launch_sketch(const SketchProblem& pb, const SketchPlan& p, void* par
     }
   }
   if (e != hipSuccess) return e;
-  const dim3 rg((unsigned)((p.n_rows + kRedRows - 1) / kRedRows), (unsigned)p.col_chunks);
+  const int64_t emax = p.n_rows * std::min(p.cpad, pb.ell);
+  const unsigned eblk = (unsigned)((emax + kRedThreads - 1) / kRedThreads);
+  double* lvl = p.nseg > 1 ? reinterpret_cast<double*>(reinterpret_cast<char*>(partial) + p.lvl_off) : nullptr;
+  const dim3 g1(eblk, (unsigned)p.nseg, (unsigned)p.col_chunks);
   if (pb.prec == kFP64)
-    hipLaunchKernelGGL(sketch_reduce_kernel<double>, rg, dim3(kRedThreads), 0, st,
-                       reinterpret_cast<const double*>(partial), p.nparts, p.n_rows, pb.ell, p.cpad,
-                       y64, y_out, out_is_double);
+    hipLaunchKernelGGL(sketch_reduce1_kernel<double>, g1, dim3(kRedThreads), 0, st,
+                       reinterpret_cast<const double*>(partial), p.nparts, p.n_rows, pb.ell, p.cpad, lvl,
+                       p.nseg, y64, y_out, out_is_double);
   else
-    hipLaunchKernelGGL(sketch_reduce_kernel<float>, rg, dim3(kRedThreads), 0, st,
-                       reinterpret_cast<const float*>(partial), p.nparts, p.n_rows, pb.ell, p.cpad,
-                       y64, y_out, out_is_double);
+    hipLaunchKernelGGL(sketch_reduce1_kernel<float>, g1, dim3(kRedThreads), 0, st,
+                       reinterpret_cast<const float*>(partial), p.nparts, p.n_rows, pb.ell, p.cpad, lvl,
+                       p.nseg, y64, y_out, out_is_double);
+  if (p.nseg > 1) {
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(sketch_reduce2_kernel, dim3((unsigned)((emax + 63) / 64), (unsigned)p.col_chunks),
+                       dim3(kRedThreads), 0, st, lvl,
+                       p.nseg, p.n_rows, pb.ell, p.cpad, y64, y_out, out_is_double);
+  }
   return hipGetLastError();
 }
 

@@ -19,17 +19,17 @@ struct SketchArgs {
   int n_out;
   int64_t o_total, o_per_wg;
   int f_blocks, ell, nparts, wm, wo, rows_per_wg, fid_f, lds_rows;
-  int64_t stage_off;  // byte offset of the per-wave staging regions (kLoadXpose)
   uint64_t seed, w2_base;
 };
 
 // Load modes of the X slab:
 //   kLoadScalar  one element per lane and slot (any strides);
 //   kLoadVecF    16-byte loads along the 32-wide f block (f contiguous);
-//   kLoadXpose   16-byte loads along the rows (mode 0, rows contiguous), each
-//                wave transposing its 16 MT x 32 slab through a private LDS
-//                region into the fragment layout.
-enum LoadMode : int { kLoadScalar = 0, kLoadVecF = 1, kLoadXpose = 2 };
+//   kLoadRowVec  mode 0 (rows contiguous): each lane loads MT consecutive rows
+//                of one f index as one vector and hands row MT n + m to the
+//                m-th row tile, i.e. the MT tiles of a wave interleave their
+//                rows, so the A fragments come straight from the loads.
+enum LoadMode : int { kLoadScalar = 0, kLoadVecF = 1, kLoadRowVec = 2 };
 
 // Reduction slot -> k offset inside the 32-wide block.  With vector loads
 // along f (the block is contiguous in memory) lane group g reads 16-byte
@@ -45,12 +45,29 @@ __device__ __forceinline__ int kmap(int g, int j) {
   }
 }
 
-// Pitch (elements) of a wave's transposed staging region [k][row]: 16 MT rows
-// plus 2, so that the fragment reads (16 consecutive rows at four k 8 apart)
-// fall on distinct banks and the 8-byte writes stay aligned.
-template <int MT>
-constexpr int xpose_pitch() {
-  return 16 * MT + 2;
+// MT consecutive elements starting at p (aligned to MT elements).
+template <typename Tin, int MT>
+__device__ __forceinline__ void load_rows(const Tin* p, Tin (&q)[MT]) {
+  if constexpr (sizeof(Tin) * MT == 16) {
+    if constexpr (sizeof(Tin) == 4) {
+      const float4 t = *reinterpret_cast<const float4*>(p);
+      q[0] = t.x;
+      q[1] = t.y;
+      q[2] = t.z;
+      q[3] = t.w;
+    } else {
+      const double2 t = *reinterpret_cast<const double2*>(p);
+      q[0] = t.x;
+      q[1] = t.y;
+    }
+  } else if constexpr (sizeof(Tin) * MT == 8 && sizeof(Tin) == 4) {
+    const float2 t = *reinterpret_cast<const float2*>(p);
+    q[0] = t.x;
+    q[1] = t.y;
+  } else {
+#pragma unroll
+    for (int m = 0; m < MT; ++m) q[m] = p[m];
+  }
 }
 
 template <typename Tin, int P, int LM, int MT, int NT>
@@ -60,6 +77,7 @@ __global__ __launch_bounds__(512) void sketch_kernel(SketchArgs a) {
   using AccT = typename Pol::AccT;
   constexpr int CP = 16 * NT;
   static_assert(CP % 4 == 0, "column chunks start at multiples of four generator columns");
+  static_assert(LM != kLoadRowVec || sizeof(Tin) * MT <= 16, "one vector load per lane and slot");
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* tab = reinterpret_cast<T*>(smem_raw);
 
@@ -75,9 +93,10 @@ __global__ __launch_bounds__(512) void sketch_kernel(SketchArgs a) {
   const int col0 = blockIdx.z * CP;
   const int64_t o_begin = orange * a.o_per_wg;
   const int64_t o_end = min(o_begin + a.o_per_wg, a.o_total);
+  const int n = lane & 15, g = lane >> 4;
 
   // Rows of each outer-mode factor that this workgroup's o range touches.
-  int64_t lo[kMaxDims];
+  int lo[kMaxDims];
   int toff[kMaxDims];
   int rows_total = 32;
 #pragma unroll
@@ -89,37 +108,44 @@ __global__ __launch_bounds__(512) void sketch_kernel(SketchArgs a) {
       // this mode: at most q1 - q0 + 1 distinct values.
       const int64_t q0 = o_begin / a.o_period[k], q1 = (o_end - 1) / a.o_period[k];
       const int64_t cnt = min(a.o_size[k], q1 - q0 + 1);
-      lo[k] = cnt == a.o_size[k] ? 0 : q0 % a.o_size[k];
+      lo[k] = cnt == a.o_size[k] ? 0 : (int)(q0 % a.o_size[k]);
       toff[k] = rows_total;
       rows_total += (int)cnt;
     }
   }
 
-  // Partial sums hold only the chunk's real columns (row stride ncz); chunks
-  // keep slots of CP columns.
+  // Output row of accumulator tile m, fragment row rr.
+  auto out_row = [&](int m, int rr) -> int64_t {
+    if constexpr (LM == kLoadRowVec)
+      return a0 + (int64_t)MT * rr + m;
+    else
+      return a0 + 16 * m + rr;
+  };
+  // One partial per workgroup (its waves are summed first); partial sums hold
+  // only the chunk's real columns (row stride ncz); chunks keep slots of CP
+  // columns.
   const int ncz = min(CP, a.ell - col0);
   AccT* part = reinterpret_cast<AccT*>(a.partial) + (int64_t)blockIdx.z * a.nparts * a.n_rows * CP +
-               ((int64_t)kg * a.wo + w_o) * a.n_rows * ncz;
-  const int n = lane & 15, g = lane >> 4;
-  Tin* stage = reinterpret_cast<Tin*>(smem_raw + a.stage_off) + (int64_t)wave * 32 * xpose_pitch<MT>();
+               (int64_t)kg * a.n_rows * ncz;
   // The host sized the LDS for lds_rows table rows.  A plan that undercounts
   // would be a planner bug: the workgroup then poisons its partial sums with
   // NaN (reported as non-finite by the QR) instead of overrunning the LDS.
   if (rows_total > a.lds_rows) {
+    if (w_o == 0) {
 #pragma unroll
-    for (int m = 0; m < MT; ++m)
+      for (int m = 0; m < MT; ++m)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int64_t row = a0 + 16 * m + Pol::out_row(g, r);
-        if (row < a.n_rows) {
+        for (int r = 0; r < 4; ++r) {
+          const int64_t row = out_row(m, Pol::out_row(g, r));
+          if (row < a.n_rows) {
 #pragma unroll
-          for (int t = 0; t < NT; ++t)
-            if (16 * t + n < ncz) part[row * ncz + 16 * t + n] = (AccT)__builtin_nan("");
+            for (int t = 0; t < NT; ++t)
+              if (16 * t + n < ncz) part[row * ncz + 16 * t + n] = (AccT)__builtin_nan("");
+          }
         }
-      }
+    }
     return;
   }
-
 
   typename Pol::Acc acc[MT][NT];
 #pragma unroll
@@ -132,7 +158,7 @@ __global__ __launch_bounds__(512) void sketch_kernel(SketchArgs a) {
   // wave starts at o_begin + w_o and advances by wo.  All uniform (SGPRs).
   struct Odo {
     int64_t o, off;
-    int64_t dig[kMaxDims];
+    int dig[kMaxDims];  // every mode size is below 2^31
   };
   auto odo_init = [&](int64_t o) {
     Odo z;
@@ -143,7 +169,7 @@ __global__ __launch_bounds__(512) void sketch_kernel(SketchArgs a) {
     for (int k = 0; k < kMaxDims; ++k) {
       z.dig[k] = 0;
       if (k < a.n_out) {
-        z.dig[k] = rem % a.o_size[k];
+        z.dig[k] = (int)(rem % a.o_size[k]);
         rem /= a.o_size[k];
         z.off += z.dig[k] * a.o_stride[k];
       }
@@ -163,80 +189,49 @@ __global__ __launch_bounds__(512) void sketch_kernel(SketchArgs a) {
           ++carry;
         }
         z.off += (dnew - z.dig[k]) * a.o_stride[k];
-        z.dig[k] = dnew;
+        z.dig[k] = (int)dnew;
       }
     }
   };
-  // A fragments of outer step z (raw input values, converted at use).
-  auto load_a = [&](Tin (&buf)[MT][8], const Odo& z) {
-    if constexpr (LM == kLoadXpose) {
-      // rows (contiguous) in 16-byte pieces: lane = (row group rg, k offset kq)
-      constexpr int V = 16 / sizeof(Tin);
-      constexpr int RG = 16 * MT / V;       // row groups of the wave's rows
-      constexpr int KQ = 64 / RG;           // k values per instruction
-      constexpr int NL = 32 / KQ;           // loads per lane
-      const int rg = lane % RG, kq = lane / RG;
-      const int64_t row = a0 + (int64_t)V * rg;
-      const bool rv = row < a.n_rows;
+  // A fragments of the outer step at element offset `off` (raw input values,
+  // converted at use).  The loads carry no conditions, so that the compiler
+  // keeps the next step's loads in flight while the current one is
+  // multiplied: rows past n_rows are clamped to the last row (their
+  // accumulator rows are never stored) and f indices past n_f to the last one
+  // (the factor table holds zeros there, so they add nothing).
+  auto load_a = [&](Tin (&buf)[MT][8], int64_t off) {
+    if constexpr (LM == kLoadRowVec) {
+      // lane (n, g): rows a0 + MT n .. a0 + MT n + MT - 1 of f index f0 + 8 g + j
+      const int64_t row = min(a0 + (int64_t)MT * n, a.n_rows - MT);  // n_rows is a multiple of MT
 #pragma unroll
-      for (int h = 0; h < NL; ++h) {
-        const int64_t kk = f0 + kq + KQ * h;
-        Tin q[V];
+      for (int j = 0; j < 8; ++j) {
+        const int64_t kk = min(f0 + 8 * g + j, a.n_f - 1);
+        Tin q[MT];
+        load_rows<Tin, MT>(X + off + row + kk * a.s_f, q);
 #pragma unroll
-        for (int v = 0; v < V; ++v) q[v] = (Tin)0;
-        if (rv && kk < a.n_f) {
-          const Tin* src = X + z.off + row + kk * a.s_f;
-          if constexpr (sizeof(Tin) == 4) {
-            const float4 t = *reinterpret_cast<const float4*>(src);
-            q[0] = t.x;
-            q[1] = t.y;
-            q[2] = t.z;
-            q[3] = t.w;
-          } else {
-            const double2 t = *reinterpret_cast<const double2*>(src);
-            q[0] = t.x;
-            q[1] = t.y;
-          }
-        }
-#pragma unroll
-        for (int v = 0; v < V; ++v) buf[(h * V + v) / 8][(h * V + v) % 8] = q[v];
+        for (int m = 0; m < MT; ++m) buf[m][j] = q[m];
       }
       return;
     }
 #pragma unroll
     for (int m = 0; m < MT; ++m) {
-      const int64_t row = a0 + 16 * m + n;
-      const bool rv = row < a.n_rows;
-      const int64_t base = z.off + row * a.s_row + f0 * a.s_f;
+      const int64_t row = min(a0 + 16 * m + n, a.n_rows - 1);
+      const int64_t base = off + row * a.s_row;
       if constexpr (LM == kLoadVecF) {
-        if constexpr (sizeof(Tin) == 4) {
+        constexpr int V = 16 / sizeof(Tin);  // n_f is a multiple of V
 #pragma unroll
-          for (int h = 0; h < 2; ++h) {
-            const int kk = 4 * g + 16 * h;
-            float4 q = make_float4(0.f, 0.f, 0.f, 0.f);
-            if (rv && f0 + kk < a.n_f) q = *reinterpret_cast<const float4*>(X + base + kk);
-            buf[m][4 * h + 0] = q.x;
-            buf[m][4 * h + 1] = q.y;
-            buf[m][4 * h + 2] = q.z;
-            buf[m][4 * h + 3] = q.w;
-          }
-        } else {
+        for (int h = 0; h < 8 / V; ++h) {
+          const int64_t kk = min(f0 + V * g + 4 * V * h, a.n_f - V);
+          Tin q[V];
+          load_rows<Tin, V>(X + base + kk, q);
 #pragma unroll
-          for (int h = 0; h < 4; ++h) {
-            const int kk = 2 * g + 8 * h;
-            double2 q = make_double2(0.0, 0.0);
-            if (rv && f0 + kk < a.n_f) q = *reinterpret_cast<const double2*>(X + base + kk);
-            buf[m][2 * h + 0] = q.x;
-            buf[m][2 * h + 1] = q.y;
-          }
+          for (int v = 0; v < V; ++v) buf[m][V * h + v] = q[v];
         }
       } else {
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
-          const int kk = 8 * g + j;
-          Tin v = (Tin)0;
-          if (rv && f0 + kk < a.n_f) v = X[base + (int64_t)kk * a.s_f];
-          buf[m][j] = v;
+          const int64_t kk = min(f0 + 8 * g + j, a.n_f - 1);
+          buf[m][j] = X[base + kk * a.s_f];
         }
       }
     }
@@ -250,7 +245,7 @@ __global__ __launch_bounds__(512) void sketch_kernel(SketchArgs a) {
     for (int k = 0; k < kMaxDims; ++k) {
       if (k < a.n_out) {
         // digit and first digit both lie in [0, o_size): one wrap at most
-        int dd = (int)(z.dig[k] - lo[k]);
+        int dd = z.dig[k] - lo[k];
         dd = dd < 0 ? dd + (int)a.o_size[k] : dd;
         const int rr = toff[k] + dd;
 #pragma unroll
@@ -265,51 +260,11 @@ __global__ __launch_bounds__(512) void sketch_kernel(SketchArgs a) {
       for (int j = 0; j < 8; ++j) v[j] = tab[kmap<Tin, LM>(g, j) * CP + 16 * t + n] * w[t];
       bf[t] = Pol::make(v);
     }
-    Tin xa[MT][8];
-    if constexpr (LM == kLoadXpose) {
-      // through the wave's staging region: [k][row], pitch xpose_pitch<MT>()
-      constexpr int V = 16 / sizeof(Tin);
-      constexpr int RG = 16 * MT / V;
-      constexpr int KQ = 64 / RG;
-      constexpr int NL = 32 / KQ;
-      constexpr int PT = xpose_pitch<MT>();
-      const int rg = lane % RG, kq = lane / RG;
-#pragma unroll
-      for (int h = 0; h < NL; ++h) {
-        Tin* d = stage + (kq + KQ * h) * PT + V * rg;
-#pragma unroll
-        for (int v = 0; v < V; v += 2) {
-          if constexpr (sizeof(Tin) == 4) {
-            *reinterpret_cast<float2*>(d + v) =
-                make_float2(buf[(h * V + v) / 8][(h * V + v) % 8], buf[(h * V + v + 1) / 8][(h * V + v + 1) % 8]);
-          } else {
-            *reinterpret_cast<double2*>(d + v) =
-                make_double2(buf[(h * V + v) / 8][(h * V + v) % 8], buf[(h * V + v + 1) / 8][(h * V + v + 1) % 8]);
-          }
-        }
-      }
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-      __builtin_amdgcn_wave_barrier();
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-#pragma unroll
-      for (int m = 0; m < MT; ++m)
-#pragma unroll
-        for (int j = 0; j < 8; ++j) xa[m][j] = stage[(8 * g + j) * PT + 16 * m + n];
-      // the next step's stores must not overtake these reads
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-      __builtin_amdgcn_wave_barrier();
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    } else {
-#pragma unroll
-      for (int m = 0; m < MT; ++m)
-#pragma unroll
-        for (int j = 0; j < 8; ++j) xa[m][j] = buf[m][j];
-    }
 #pragma unroll
     for (int m = 0; m < MT; ++m) {
       T v[8];
 #pragma unroll
-      for (int j = 0; j < 8; ++j) v[j] = (T)xa[m][j];
+      for (int j = 0; j < 8; ++j) v[j] = (T)buf[m][j];
       const typename Pol::Frag af = Pol::make(v);
 #pragma unroll
       for (int t = 0; t < NT; ++t) Pol::mma(acc[m][t], af, bf[t]);
@@ -320,7 +275,7 @@ __global__ __launch_bounds__(512) void sketch_kernel(SketchArgs a) {
   // multiplied (two register buffers, alternating).
   Tin bufA[MT][8], bufB[MT][8];
   Odo cur = odo_init(o_begin + w_o);
-  if (cur.o < o_end) load_a(bufA, cur);
+  load_a(bufA, cur.o < o_end ? cur.off : 0);
   // The factor table is drawn while the first slab loads are in flight.
   // Draw the factor rows (fp64 Gaussians rounded to the working precision),
   // four columns per generator call (the chunk start is a multiple of four),
@@ -334,17 +289,17 @@ __global__ __launch_bounds__(512) void sketch_kernel(SketchArgs a) {
     for (int kk = 1; kk < kMaxDims; ++kk)
       if (kk < a.n_out && r >= toff[kk]) k = kk;
     const bool fr = r < 32;
-    int dd = (int)lo[k] + (r - toff[k]);
+    int dd = lo[k] + (r - toff[k]);
     dd = dd >= (int)a.o_size[k] ? dd - (int)a.o_size[k] : dd;
     const int64_t row = fr ? f0 + r : (int64_t)dd;
     const uint64_t fid = fr ? (uint64_t)a.fid_f : (uint64_t)a.o_fid[k];
     const bool live = !fr || row < a.n_f;
-    double g[4];
-    gauss_quad(a.seed, a.w2_base | fid, 0, row, (uint64_t)((col0 >> 2) + jq), g);
+    double gq[4];
+    gauss_quad(a.seed, a.w2_base | fid, 0, row, (uint64_t)((col0 >> 2) + jq), gq);
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       const int c = 4 * jq + u;
-      tab[r * CP + c] = (live && c < ncol) ? factor_value<P>(g[u]) : (T)0;
+      tab[r * CP + c] = (live && c < ncol) ? factor_value<P>(gq[u]) : (T)0;
     }
   }
   for (int e = threadIdx.x; e < rows_total * (CP - 4 * nq); e += blockDim.x) {
@@ -355,24 +310,53 @@ __global__ __launch_bounds__(512) void sketch_kernel(SketchArgs a) {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
   __builtin_amdgcn_s_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+  // (past the end of the range the prefetch re-reads the current step)
   while (cur.o < o_end) {
     Odo nxt = cur;
     odo_step(nxt, a.wo);
-    if (nxt.o < o_end) load_a(bufB, nxt);
+    load_a(bufB, nxt.o < o_end ? nxt.off : cur.off);
     compute(bufA, cur);
     cur = nxt;
     if (cur.o >= o_end) break;
     odo_step(nxt, a.wo);
-    if (nxt.o < o_end) load_a(bufA, nxt);
+    load_a(bufA, nxt.o < o_end ? nxt.off : cur.off);
     compute(bufB, cur);
     cur = nxt;
   }
 
+  if (a.wo > 1) {
+    // The waves that share rows (same w_m) are summed in fp64 in wave order
+    // through LDS (the factor table is no longer needed), and wave w_o = 0
+    // writes the workgroup's partial.
+    double* red = reinterpret_cast<double*>(smem_raw) + (int64_t)w_m * (MT * NT * 4 * 64);
+    __syncthreads();
+    for (int w = 0; w < a.wo; ++w) {
+      if (w_o == w) {
+#pragma unroll
+        for (int m = 0; m < MT; ++m)
+#pragma unroll
+          for (int t = 0; t < NT; ++t)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+              double* s = &red[((m * NT + t) * 4 + r) * 64 + lane];
+              *s = (w == 0 ? 0.0 : *s) + (double)acc[m][t][r];
+            }
+      }
+      __syncthreads();
+    }
+    if (w_o != 0) return;
+#pragma unroll
+    for (int m = 0; m < MT; ++m)
+#pragma unroll
+      for (int t = 0; t < NT; ++t)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) acc[m][t][r] = (AccT)red[((m * NT + t) * 4 + r) * 64 + lane];
+  }
 #pragma unroll
   for (int m = 0; m < MT; ++m)
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      const int64_t row = a0 + 16 * m + Pol::out_row(g, r);
+      const int64_t row = out_row(m, Pol::out_row(g, r));
       if (row < a.n_rows) {
 #pragma unroll
         for (int t = 0; t < NT; ++t)
@@ -381,6 +365,10 @@ __global__ __launch_bounds__(512) void sketch_kernel(SketchArgs a) {
     }
 }
 
+// Bytes of LDS the end-of-kernel wave reduction needs (fp64, wm row groups).
+inline size_t wave_reduce_lds(int wm, int wo, int mt, int nt) {
+  return wo > 1 ? (size_t)wm * mt * nt * 4 * 64 * sizeof(double) : 0;
+}
 
 template <typename Tin, int P, int LM, int MT, int NT>
 hipError_t launch_inst(const SketchArgs& args, dim3 grid, int threads, size_t lds, hipStream_t st) {
@@ -409,7 +397,12 @@ hipError_t dispatch_mt(int mt, int nt, const SketchArgs& args, dim3 grid, int th
   switch (mt) {
     case 1: return dispatch_nt<Tin, P, LM, 1>(nt, args, grid, threads, lds, st);
     case 2: return dispatch_nt<Tin, P, LM, 2>(nt, args, grid, threads, lds, st);
-    default: return dispatch_nt<Tin, P, LM, 4>(nt, args, grid, threads, lds, st);
+    default:
+      if constexpr (LM == kLoadRowVec && sizeof(Tin) == 8) {
+        return hipErrorInvalidValue;  // a row vector of four doubles is not one load
+      } else {
+        return dispatch_nt<Tin, P, LM, 4>(nt, args, grid, threads, lds, st);
+      }
   }
 }
 
@@ -417,10 +410,9 @@ template <typename Tin, int P>
 hipError_t dispatch_lm(int lm, int mt, int nt, const SketchArgs& args, dim3 grid, int threads,
                        size_t lds, hipStream_t st) {
   if (lm == kLoadVecF) return dispatch_mt<Tin, P, kLoadVecF>(mt, nt, args, grid, threads, lds, st);
-  if (lm == kLoadXpose) return dispatch_mt<Tin, P, kLoadXpose>(mt, nt, args, grid, threads, lds, st);
+  if (lm == kLoadRowVec) return dispatch_mt<Tin, P, kLoadRowVec>(mt, nt, args, grid, threads, lds, st);
   return dispatch_mt<Tin, P, kLoadScalar>(mt, nt, args, grid, threads, lds, st);
 }
-
 
 // Per-policy entry points (one translation unit each).
 hipError_t dispatch_fp64(bool x_double, int lm, int mt, int nt, const SketchArgs& args, dim3 grid,
