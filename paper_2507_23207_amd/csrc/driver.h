@@ -37,6 +37,8 @@ struct SketchSet {
   int nmodes = 0, out_double = 0;
   SketchProblem pb[kMaxDims];
   SketchPlan pl[kMaxDims];
+  bool fused = false;  // one pass over X for all the modes
+  FusedPlan fplan;
   size_t ws_bytes = 0;
 };
 int prepare_sketches(const void* X, int dtype, int d, const int64_t* dims, int nmodes,

@@ -69,6 +69,36 @@ bool cached_tile(const SketchProblem& pb, SketchTile* out);
 hipError_t launch_sketch(const SketchProblem& pb, const SketchPlan& plan, void* partial,
                          double* y64, void* y_out, int out_is_double, hipStream_t st);
 
+// Deterministic fp64 reduction of per-workgroup partial sums: `partial` holds,
+// per column chunk z of width cp, nparts blocks of n_rows x ncz_z values
+// (ncz_z = min(cp, ell - z cp)), fp32 (acc_double: fp64); Y (n_rows x ell,
+// column-major) goes to y64 and/or y_out.  `lvl` holds
+// partial_reduce_lvl_bytes() bytes of level-1 sums.
+size_t partial_reduce_lvl_bytes(int nparts, int64_t n_rows, int cp, int col_chunks);
+hipError_t launch_partial_reduce(const void* partial, bool acc_double, int nparts, int64_t n_rows, int ell,
+                                 int cp, int col_chunks, void* lvl, double* y64, void* y_out,
+                                 int out_is_double, hipStream_t st);
+
+// One pass over X for several mode sketches of the same tensor (all-mode
+// fused kernel); see fused.hip.
+struct FusedPlan {
+  bool ok = false;
+  alignas(8) unsigned char args[2560];
+  size_t args_bytes = 0;
+  int nt = 0;
+  size_t lds = 0;
+  int64_t grid_x = 0;
+  int grid_y = 0;
+  int64_t nparts[kMaxDims] = {0};
+  size_t part_off[kMaxDims] = {0}, lvl_off[kMaxDims] = {0};
+  size_t ws_bytes = 0;
+};
+FusedPlan plan_fused(const SketchProblem* pbs, int nmodes);
+// y64[j] / y_out[j] (either may be null, or the arrays themselves) receive the
+// sketch of pbs[j]; ws holds fp.ws_bytes.
+hipError_t launch_fused(const FusedPlan& fp, const SketchProblem* pbs, int nmodes, void* ws,
+                        double* const* y64, void* const* y_out, int out_is_double, hipStream_t st);
+
 // Fills out (rows x cols, column-major) with the factor entries of the RNG
 // spec in precision prec (0 fp64, 1 fp32, 2 bf16 bits, 3 bf16 hi plane then
 // lo plane).

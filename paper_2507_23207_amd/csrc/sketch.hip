@@ -284,24 +284,36 @@ hipError_t launch_sketch(const SketchProblem& pb, const SketchPlan& p, void* par
     }
   }
   if (e != hipSuccess) return e;
-  const int64_t emax = p.n_rows * std::min(p.cpad, pb.ell);
+  return launch_partial_reduce(partial, pb.prec == kFP64, p.nparts, p.n_rows, pb.ell, p.cpad, p.col_chunks,
+                               reinterpret_cast<char*>(partial) + p.lvl_off, y64, y_out, out_is_double, st);
+}
+
+size_t partial_reduce_lvl_bytes(int nparts, int64_t n_rows, int cp, int col_chunks) {
+  const int nseg = (nparts + kRedSeg - 1) / kRedSeg;
+  return nseg > 1 ? (size_t)col_chunks * nseg * n_rows * cp * sizeof(double) : 0;
+}
+
+hipError_t launch_partial_reduce(const void* partial, bool acc_double, int nparts, int64_t n_rows, int ell,
+                                 int cp, int col_chunks, void* lvl_buf, double* y64, void* y_out,
+                                 int out_is_double, hipStream_t st) {
+  const int nseg = (nparts + kRedSeg - 1) / kRedSeg;
+  const int64_t emax = n_rows * std::min(cp, ell);
   const unsigned eblk = (unsigned)((emax + kRedThreads - 1) / kRedThreads);
-  double* lvl = p.nseg > 1 ? reinterpret_cast<double*>(reinterpret_cast<char*>(partial) + p.lvl_off) : nullptr;
-  const dim3 g1(eblk, (unsigned)p.nseg, (unsigned)p.col_chunks);
-  if (pb.prec == kFP64)
+  double* lvl = nseg > 1 ? reinterpret_cast<double*>(lvl_buf) : nullptr;
+  const dim3 g1(eblk, (unsigned)nseg, (unsigned)col_chunks);
+  if (acc_double)
     hipLaunchKernelGGL(sketch_reduce1_kernel<double>, g1, dim3(kRedThreads), 0, st,
-                       reinterpret_cast<const double*>(partial), p.nparts, p.n_rows, pb.ell, p.cpad, lvl,
-                       p.nseg, y64, y_out, out_is_double);
+                       reinterpret_cast<const double*>(partial), nparts, n_rows, ell, cp, lvl, nseg, y64, y_out,
+                       out_is_double);
   else
     hipLaunchKernelGGL(sketch_reduce1_kernel<float>, g1, dim3(kRedThreads), 0, st,
-                       reinterpret_cast<const float*>(partial), p.nparts, p.n_rows, pb.ell, p.cpad, lvl,
-                       p.nseg, y64, y_out, out_is_double);
-  if (p.nseg > 1) {
-    e = hipGetLastError();
+                       reinterpret_cast<const float*>(partial), nparts, n_rows, ell, cp, lvl, nseg, y64, y_out,
+                       out_is_double);
+  if (nseg > 1) {
+    hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(sketch_reduce2_kernel, dim3((unsigned)((emax + 63) / 64), (unsigned)p.col_chunks),
-                       dim3(kRedThreads), 0, st, lvl,
-                       p.nseg, p.n_rows, pb.ell, p.cpad, y64, y_out, out_is_double);
+    hipLaunchKernelGGL(sketch_reduce2_kernel, dim3((unsigned)((emax + 63) / 64), (unsigned)col_chunks),
+                       dim3(kRedThreads), 0, st, lvl, nseg, n_rows, ell, cp, y64, y_out, out_is_double);
   }
   return hipGetLastError();
 }

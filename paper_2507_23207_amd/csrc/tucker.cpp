@@ -56,6 +56,11 @@ struct TuckerSetup {
   size_t off_core[2]{}, off_err[2]{}, off_trunc = 0;
   size_t total = 0;
   TruncPlan trunc;
+  // Algorithm 7 with the all-mode fused sketch: one pass over X leaves every
+  // mode's sketch (y64 of mode m at off_y64 + y_off[m] doubles)
+  bool fused = false;
+  FusedPlan fplan;
+  size_t y_off[kMaxDims]{};
 };
 
 int plan_tucker(bool sthosvd, int dtype, int d, const int64_t* dims, const int32_t* rank,
@@ -124,6 +129,21 @@ int plan_tucker(bool sthosvd, int dtype, int d, const int64_t* dims, const int32
     }
   }
   s.n_sketch = d;
+  if (!sthosvd && dtype == KRP_F32) {
+    SketchProblem all[kMaxDims];
+    for (int k = 0; k < d; ++k) all[k] = s.spb[k];
+    s.fplan = plan_fused(all, d);
+    s.fused = s.fplan.ok;
+    if (s.fused) {
+      part_max = std::max(part_max, s.fplan.ws_bytes);
+      size_t yo = 0;
+      for (int k = 0; k < d; ++k) {
+        s.y_off[k] = yo;
+        yo += (size_t)dims[k] * s.ell[k];
+      }
+      y_max = std::max(y_max, yo);
+    }
+  }
   // TTM chain of Algorithm 7 (natural order) and of the error check.
   for (int k = 0; k < d; ++k) cur[k] = dims[k];
   for (int step = 0; step < d; ++step) {
@@ -178,6 +198,7 @@ std::string tucker_key(const TuckerSetup& s, const krp_opts& o, const void* X, c
        "|X=" + ptr_key(X) + "|core=" + ptr_key(core) + "|ws=" + ptr_key(ws) + "|" +
        "|st=" + ptr_key(status);
   for (int i = 0; i < s.n_sketch; ++i) k += "|t=" + plan_key(s.spl[i]);  // tilings (tuned or not)
+  k += s.fused ? "|fused" : "";
   return k;
 }
 
@@ -204,16 +225,31 @@ int enqueue_tucker(TuckerSetup& s, const krp_opts& o, const void* X, void* core,
   void* cores[2] = {ws + s.off_core[0], ws + s.off_core[1]};
   const void* cur = X;
   bool cur64 = x64;
+  if (s.fused) {
+    // every sketch of Algorithm 7 from one pass over X
+    SketchProblem all[kMaxDims];
+    double* ys[kMaxDims];
+    for (int k = 0; k < d; ++k) {
+      all[k] = s.spb[k];
+      all[k].x = X;
+      ys[k] = y64 + s.y_off[k];
+    }
+    KRP_TRY(check(launch_fused(s.fplan, all, d, part, ys, nullptr, 0, st), "fused sketch"));
+  }
   for (int step = 0; step < d; ++step) {
     const int m = s.spb[step].mode;
     SketchProblem pb = s.spb[step];
     pb.x = s.sthosvd ? cur : X;
     pb.x_is_double = s.sthosvd ? (cur64 ? 1 : 0) : (x64 ? 1 : 0);
-    if (tune) {
-      const SketchPlan t = plan_sketch(pb, tuned_tile(pb, st));
-      if (t.partial_bytes <= s.spl[step].partial_bytes) s.spl[step] = t;
+    if (s.fused) {
+      y64 = reinterpret_cast<double*>(ws + s.off_y64) + s.y_off[m];
+    } else {
+      if (tune) {
+        const SketchPlan t = plan_sketch(pb, tuned_tile(pb, st));
+        if (t.partial_bytes <= s.spl[step].partial_bytes) s.spl[step] = t;
+      }
+      KRP_TRY(check(launch_sketch(pb, s.spl[step], part, y64, nullptr, 0, st), "sketch"));
     }
-    KRP_TRY(check(launch_sketch(pb, s.spl[step], part, y64, nullptr, 0, st), "sketch"));
     double* q64 = reinterpret_cast<double*>(ws + s.off_q64[m]);
     // the partial-sum buffer of the sketch is free again: workspace of the QR
     KRP_TRY(check(launch_cholqr_split(pb.dims[m], s.ell[m], y64, q64, trunc ? nullptr : Q[m], x64 ? 1 : 0,
@@ -312,6 +348,7 @@ int enqueue_tucker(TuckerSetup& s, const krp_opts& o, const void* X, void* core,
 // without the flag stay valid).  Returns true when some sketch of the sweep
 // has no entry yet.  Launches nothing.
 bool apply_cached_tiles(TuckerSetup& s, const void* X, char* ws) {
+  if (s.fused) return false;  // the fused pass has no tiling to tune
   bool missing = false;
   for (int step = 0; step < s.n_sketch; ++step) {
     SketchProblem pb = s.spb[step];
@@ -348,6 +385,7 @@ int tucker_entry(bool sthosvd, const void* X, int dtype, int d, const int64_t* d
     if (!Q[k]) return set_error(KRP_EINVAL, "Q[%d] is NULL", k);
   TuckerSetup s;
   KRP_TRY(plan_tucker(sthosvd, dtype, d, dims, rank, oversample, o, s));
+  if (s.fused && (reinterpret_cast<uintptr_t>(X) & 15) != 0) s.fused = false;  // the fused pass loads 16-byte rows
   if (core_dims)
     for (int k = 0; k < d; ++k) core_dims[k] = o.truncate ? s.rank[k] : s.ell[k];
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
@@ -418,11 +456,21 @@ int prepare_sketches(const void* X, int dtype, int d, const int64_t* dims, int n
     }
     part = std::max(part, ss.pl[j].partial_bytes);
   }
+  // several modes of the same tensor: one fused pass over X when it applies
+  ss.fused = false;
+  if (nmodes >= 2) {
+    ss.fplan = plan_fused(ss.pb, nmodes);
+    if (ss.fplan.ok) {
+      ss.fused = true;
+      part = ss.fplan.ws_bytes;
+    }
+  }
   ss.ws_bytes = align_up(part);
   return KRP_OK;
 }
 
 int enqueue_sketches(const SketchSet& ss, char* ws, void* const* Y, hipStream_t st) {
+  if (ss.fused) return check(launch_fused(ss.fplan, ss.pb, ss.nmodes, ws, nullptr, Y, ss.out_double, st), "fused sketch");
   for (int j = 0; j < ss.nmodes; ++j)
     KRP_TRY(check(launch_sketch(ss.pb[j], ss.pl[j], ws, nullptr, Y[j], ss.out_double, st), "sketch"));
   return KRP_OK;
@@ -454,6 +502,7 @@ int krp_sketch(const void* X, int dtype, int d, const int64_t* dims, int nmodes,
   for (int j = 0; j < nmodes; ++j)
     key += "|" + std::to_string(modes[j]) + "," + std::to_string(ell[j]) + "," + ptr_key(Y[j]) + ",t=" +
            plan_key(ss.pl[j]);
+  key += ss.fused ? "|fused" : "";
   return run_maybe_graph(key, !(o.flags & KRP_FLAG_NO_GRAPH), st,
                          [&](hipStream_t cs) -> int { return enqueue_sketches(ss, ws, Y, cs); });
 }
@@ -484,17 +533,21 @@ int krp_workspace_size(int which, int dtype, int d, const int64_t* dims, const i
   o.prec = prec;
   if (which == 0) {
     size_t part = 0;
+    SketchProblem all[kMaxDims];
     for (int m = 0; m < d; ++m) {
       if (rank[m] < 1 || rank[m] > kMaxEll) return set_error(KRP_EINVAL, "ell[%d] outside 1..64", m);
-      SketchProblem pb;
+      SketchProblem& pb = all[m];
       pb.x_is_double = dtype == KRP_F64;
       pb.d = d;
       for (int k = 0; k < d; ++k) pb.dims[k] = dims[k];
       pb.mode = m;
       pb.ell = rank[m];
       pb.prec = prec;
+      pb.sketch_id = (uint32_t)m;
       part = std::max(part, plan_sketch(pb, SketchTile{}).partial_bytes);
     }
+    const FusedPlan fp = plan_fused(all, d);  // the call with all modes takes the fused pass
+    if (fp.ok) part = std::max(part, fp.ws_bytes);
     *bytes = align_up(part);
     return KRP_OK;
   }
