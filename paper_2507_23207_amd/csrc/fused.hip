@@ -34,7 +34,7 @@ namespace {
 
 constexpr int kFuWaves = 8;
 constexpr int kFuMaxSeg = 64;
-constexpr int kStagePitch = 68;  // floats per staged i1 column: 64 rows of i0 + 4
+constexpr int kStagePitch = 36;  // floats per staged i1 column: 32 rows of i0 + 4
 constexpr size_t kFuLdsMax = 160 * 1024;
 
 struct FusedArgs {
@@ -57,20 +57,47 @@ struct FusedArgs {
   int off_f[kMaxDims];        // per sketch m: Omega^(m)_1 rows (i1 block)
   int off_r[kMaxDims];        // per sketch m: Omega^(m)_0 rows (i0 block)
   int off_o[kMaxDims][kMaxDims];  // per sketch m and outer mode k: Omega^(m)_{k+2} rows (box)
-  int stage_off, acc_off, acc_rows;
+  int frag_off, stage_off, acc_off, acc_rows;
   int acc_row0[kMaxDims];     // per outer mode k sketched: first accumulator row
   float* part[kMaxDims];      // per sketch m: partial sums [part][n_m][ell_m]
 };
 
-template <int P, int NT>
+// Fragments of the factor operands that do not change along the outer loop
+// (Omega^(0)_1, Omega^(m)_1 for outer m, Omega^(1)_0) are split once into the
+// policy's MFMA fragments and kept in LDS as 16-byte chunks [frag][chunk][lane].
+template <int P>
+struct FragStore {
+  using Frag = typename Policy<P>::Frag;
+  static constexpr int NC = (int)(sizeof(Frag) / 16);
+  static_assert(sizeof(Frag) % 16 == 0, "fragments are whole 16-byte chunks");
+  __device__ static void put(unsigned char* base, int id, int lane, const Frag& f) {
+    uint4 c[NC];
+    __builtin_memcpy(c, &f, sizeof(Frag));
+#pragma unroll
+    for (int k = 0; k < NC; ++k) reinterpret_cast<uint4*>(base)[(id * NC + k) * 64 + lane] = c[k];
+  }
+  __device__ static Frag get(const unsigned char* base, int id, int lane) {
+    uint4 c[NC];
+#pragma unroll
+    for (int k = 0; k < NC; ++k) c[k] = reinterpret_cast<const uint4*>(base)[(id * NC + k) * 64 + lane];
+    Frag f;
+    __builtin_memcpy(&f, c, sizeof(Frag));
+    return f;
+  }
+};
+
+template <int P, int NT, int NOUT>
 __global__ __launch_bounds__(512) void fused_sketch_kernel(FusedArgs a) {
   using Pol = Policy<P>;
   using T = typename Pol::T;
+  using FS = FragStore<P>;
   static_assert(sizeof(T) == 4, "fp32, bf16 and split-bf16 policies");
   constexpr int MT = 4;
   constexpr int CP = 16 * NT;
+  constexpr int TP = CP + 1;  // table pitch: the lane groups' row reads fall on distinct banks
   extern __shared__ __align__(16) unsigned char smem[];
   T* tab = reinterpret_cast<T*>(smem);
+  unsigned char* frg = smem + a.frag_off;
 
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -83,22 +110,17 @@ __global__ __launch_bounds__(512) void fused_sketch_kernel(FusedArgs a) {
   float* accl = reinterpret_cast<float*>(smem + a.acc_off) + wave * a.acc_rows * CP;
 
   // the workgroup's box of outer indices: [lo_k, lo_k + rr_k) per outer mode
-  int lo[kMaxDims], rr[kMaxDims], bc[kMaxDims];
-  int64_t nsteps = 1;
+  int lo[NOUT + 1], rr[NOUT + 1], bc[NOUT + 1];
+  int nsteps = 1;
   {
     int64_t rem = box_id;
 #pragma unroll
-    for (int k = 0; k < kMaxDims; ++k) {
-      lo[k] = 0;
-      rr[k] = 1;
-      bc[k] = 0;
-      if (k < a.n_out) {
-        bc[k] = (int)(rem % a.nbox[k]);
-        rem /= a.nbox[k];
-        lo[k] = bc[k] * a.box[k];
-        rr[k] = (int)min((int64_t)a.box[k], a.o_size[k] - lo[k]);
-        nsteps *= rr[k];
-      }
+    for (int k = 0; k < NOUT; ++k) {
+      bc[k] = (int)(rem % a.nbox[k]);
+      rem /= a.nbox[k];
+      lo[k] = bc[k] * a.box[k];
+      rr[k] = (int)min((int64_t)a.box[k], a.o_size[k] - lo[k]);
+      nsteps *= rr[k];
     }
   }
 
@@ -110,7 +132,7 @@ __global__ __launch_bounds__(512) void fused_sketch_kernel(FusedArgs a) {
     while (s + 1 < a.nseg && r >= a.seg_off[s + 1]) ++s;
     const int kind = a.seg_kind[s];
     const int idx = r - a.seg_off[s];
-    int64_t row, limit;
+    int64_t row = 0, limit = 0;
     bool inbox = true;
     if (kind == 0) {
       row = f0 + idx;
@@ -119,11 +141,8 @@ __global__ __launch_bounds__(512) void fused_sketch_kernel(FusedArgs a) {
       row = a0 + idx;
       limit = a.n0;
     } else {
-      // (unrolled selection keeps the per-mode arrays in registers)
-      row = 0;
-      limit = 0;
 #pragma unroll
-      for (int k = 0; k < kMaxDims; ++k)
+      for (int k = 0; k < NOUT; ++k)
         if (k == kind - 2) {
           row = lo[k] + idx;
           limit = a.o_size[k];
@@ -138,10 +157,41 @@ __global__ __launch_bounds__(512) void fused_sketch_kernel(FusedArgs a) {
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       const int c = 4 * q + u;
-      tab[r * CP + c] = (live && c < a.ell[m]) ? (T)gq[u] : (T)0;
+      tab[r * TP + c] = (live && c < a.ell[m]) ? (T)gq[u] : (T)0;
     }
   }
   for (int e = lane; e < a.acc_rows * CP; e += 64) accl[e] = 0.f;
+  __syncthreads();
+  // Static fragments: frag ids  [0, NT) mode 0's B (Omega^(0)_1),
+  // [NT (1 + k), NT (2 + k)) outer sketch k's B (Omega^(k+2)_1),
+  // [NT (1 + NOUT) + 2 t + kc] mode 1's A (Omega^(1)_0, i0 chunk kc).
+  const bool want0 = a.want & 1, want1 = (a.want >> 1) & 1;
+  for (int e = threadIdx.x; e < NT * (3 + NOUT) * 64; e += blockDim.x) {
+    const int id = e / 64, l = e % 64;
+    const int ln = l & 15, lg = l >> 4;
+    T v[8];
+    int base = -1, t = 0, kc = 0;
+    bool amode = false;
+    if (id < NT) {
+      if (want0) base = a.off_f[0];
+      t = id;
+    } else if (id < NT * (1 + NOUT)) {
+      const int k = id / NT - 1;
+      if ((a.want >> (k + 2)) & 1) base = a.off_f[k + 2];
+      t = id % NT;
+    } else {
+      const int j2 = id - NT * (1 + NOUT);
+      t = j2 / 2;
+      kc = j2 % 2;
+      amode = true;
+      if (want1) base = a.off_r[1];
+    }
+    if (base < 0) continue;
+#pragma unroll
+    for (int j = 0; j < 8; ++j)
+      v[j] = amode ? tab[(base + 32 * kc + 8 * lg + j) * TP + 16 * t + ln] : tab[(base + 8 * lg + j) * TP + 16 * t + ln];
+    FS::put(frg, id, l, Pol::make(v));
+  }
 
   const float* X = a.x;
   // lane (n, g): rows a0 + 4 n .. a0 + 4 n + 3 of i1 = f0 + 8 g + j (clamped:
@@ -160,22 +210,20 @@ __global__ __launch_bounds__(512) void fused_sketch_kernel(FusedArgs a) {
   };
   // step odometer over the box (digits dig_k in [0, rr_k)), uniform
   struct Odo {
-    int64_t s, off;
-    int dig[kMaxDims];
+    int s;
+    int64_t off;
+    int dig[NOUT + 1];
   };
-  auto odo_init = [&](int64_t s) {
+  auto odo_init = [&](int s) {
     Odo z;
     z.s = s;
     z.off = 0;
-    int64_t rem = s;
+    int rem = s;
 #pragma unroll
-    for (int k = 0; k < kMaxDims; ++k) {
-      z.dig[k] = 0;
-      if (k < a.n_out) {
-        z.dig[k] = (int)(rem % rr[k]);
-        rem /= rr[k];
-        z.off += (int64_t)(lo[k] + z.dig[k]) * a.o_stride[k];
-      }
+    for (int k = 0; k < NOUT; ++k) {
+      z.dig[k] = rem % rr[k];
+      rem /= rr[k];
+      z.off += (int64_t)(lo[k] + z.dig[k]) * a.o_stride[k];
     }
     return z;
   };
@@ -183,25 +231,23 @@ __global__ __launch_bounds__(512) void fused_sketch_kernel(FusedArgs a) {
     z.s += by;
     int carry = by;
 #pragma unroll
-    for (int k = 0; k < kMaxDims; ++k) {
-      if (k < a.n_out && carry != 0) {
-        int dn = z.dig[k] + carry;
-        carry = 0;
-        while (dn >= rr[k]) {
-          dn -= rr[k];
-          ++carry;
-        }
-        z.off += (int64_t)(dn - z.dig[k]) * a.o_stride[k];
-        z.dig[k] = dn;
+    for (int k = 0; k < NOUT; ++k) {
+      int dn = z.dig[k] + carry;
+      carry = 0;
+      while (dn >= rr[k]) {
+        dn -= rr[k];
+        ++carry;
       }
+      z.off += (int64_t)(dn - z.dig[k]) * a.o_stride[k];
+      z.dig[k] = dn;
     }
   };
-  // product over the outer modes (except `skip`) of sketch m's factor rows at the step's digits
+  // product over the outer modes (except `skip`) of sketch m's factor rows at column col
   auto outer_weight = [&](const Odo& z, int m, int skip, int col) {
-    T w = (T)1;
+    float w = 1.f;
 #pragma unroll
-    for (int k = 0; k < kMaxDims; ++k)
-      if (k < a.n_out && k != skip) w = w * tab[(a.off_o[m][k] + z.dig[k]) * CP + col];
+    for (int k = 0; k < NOUT; ++k)
+      if (k != skip) w *= (float)tab[(a.off_o[m][k] + z.dig[k]) * TP + col];
     return w;
   };
 
@@ -214,7 +260,6 @@ __global__ __launch_bounds__(512) void fused_sketch_kernel(FusedArgs a) {
     acc1[t][0] = Pol::zero();
     acc1[t][1] = Pol::zero();
   }
-  const bool want0 = a.want & 1, want1 = (a.want >> 1) & 1;
 
   auto compute = [&](const float (&buf)[MT][8], const Odo& z) {
     typename Pol::Frag af[MT];
@@ -226,27 +271,27 @@ __global__ __launch_bounds__(512) void fused_sketch_kernel(FusedArgs a) {
       af[m] = Pol::make(v);
     }
     if (want0) {
+      // the step's weight is applied to the product: acc += W^(0)[o, c] (S Omega^(0)_1)
 #pragma unroll
       for (int t = 0; t < NT; ++t) {
-        const T w = outer_weight(z, 0, -1, 16 * t + n);
-        T v[8];
+        const typename Pol::Frag bf = FS::get(frg, t, lane);
+        const float w = outer_weight(z, 0, -1, 16 * t + n);
 #pragma unroll
-        for (int j = 0; j < 8; ++j) v[j] = tab[(a.off_f[0] + 8 * g + j) * CP + 16 * t + n] * w;
-        const typename Pol::Frag bf = Pol::make(v);
+        for (int m = 0; m < MT; ++m) {
+          typename Pol::Acc u = Pol::zero();
+          Pol::mma(u, af[m], bf);
 #pragma unroll
-        for (int m = 0; m < MT; ++m) Pol::mma(acc0[m][t], af[m], bf);
+          for (int r = 0; r < 4; ++r) acc0[m][t][r] += w * u[r];
+        }
       }
     }
 #pragma unroll
-    for (int k = 0; k < kMaxDims - 2; ++k) {
+    for (int k = 0; k < NOUT; ++k) {
       const int ms = k + 2;
-      if (k >= a.n_out || !((a.want >> ms) & 1)) continue;
+      if (!((a.want >> ms) & 1)) continue;
 #pragma unroll
       for (int t = 0; t < NT; ++t) {
-        T v[8];
-#pragma unroll
-        for (int j = 0; j < 8; ++j) v[j] = tab[(a.off_f[ms] + 8 * g + j) * CP + 16 * t + n];
-        const typename Pol::Frag bf = Pol::make(v);
+        const typename Pol::Frag bf = FS::get(frg, NT * (1 + k) + t, lane);
         float ts = 0.f;
 #pragma unroll
         for (int m = 0; m < MT; ++m) {
@@ -254,54 +299,65 @@ __global__ __launch_bounds__(512) void fused_sketch_kernel(FusedArgs a) {
           Pol::mma(u, af[m], bf);
 #pragma unroll
           for (int r = 0; r < 4; ++r)
-            ts += u[r] * (float)tab[(a.off_r[ms] + 4 * Pol::out_row(g, r) + m) * CP + 16 * t + n];
+            ts += u[r] * (float)tab[(a.off_r[ms] + 4 * Pol::out_row(g, r) + m) * TP + 16 * t + n];
         }
         ts += __shfl_xor(ts, 16, 64);
         ts += __shfl_xor(ts, 32, 64);
         if (g == 0) {
-          const float w = (float)outer_weight(z, ms, k, 16 * t + n);
           float* dst = &accl[(a.acc_row0[k] + z.dig[k]) * CP + 16 * t + n];
-          *dst += ts * w;
+          *dst += ts * outer_weight(z, ms, k, 16 * t + n);
         }
       }
     }
     if (want1) {
-      // slab into the wave's staging region as [i1][i0]
+      // the slab, half at a time (i0 rows 32 kc .. 32 kc + 31), into the
+      // wave's staging region as [i1][i0]; the lanes holding those rows write
+      typename Pol::Acc u1[NT][2];
 #pragma unroll
-      for (int j = 0; j < 8; ++j)
-        *reinterpret_cast<float4*>(&stage[(8 * g + j) * kStagePitch + 4 * n]) =
-            make_float4(buf[0][j], buf[1][j], buf[2][j], buf[3][j]);
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-      __builtin_amdgcn_wave_barrier();
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-      T w1[NT];
-#pragma unroll
-      for (int t = 0; t < NT; ++t) w1[t] = outer_weight(z, 1, -1, 16 * t + n);
+      for (int t = 0; t < NT; ++t) {
+        u1[t][0] = Pol::zero();
+        u1[t][1] = Pol::zero();
+      }
 #pragma unroll
       for (int kc = 0; kc < 2; ++kc) {
+        if ((n >> 3) == kc) {
+#pragma unroll
+          for (int j = 0; j < 8; ++j)
+            *reinterpret_cast<float4*>(&stage[(8 * g + j) * kStagePitch + 4 * (n & 7)]) =
+                make_float4(buf[0][j], buf[1][j], buf[2][j], buf[3][j]);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         typename Pol::Frag bs[2];
 #pragma unroll
         for (int nt = 0; nt < 2; ++nt) {
-          const float* src = &stage[(16 * nt + n) * kStagePitch + 32 * kc + 8 * g];
+          const float* src = &stage[(16 * nt + n) * kStagePitch + 8 * g];
           const float4 p0 = *reinterpret_cast<const float4*>(src);
           const float4 p1 = *reinterpret_cast<const float4*>(src + 4);
           const T v[8] = {p0.x, p0.y, p0.z, p0.w, p1.x, p1.y, p1.z, p1.w};
           bs[nt] = Pol::make(v);
         }
+        // the next half's staging writes must not overtake these reads
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 #pragma unroll
         for (int t = 0; t < NT; ++t) {
-          T v[8];
-#pragma unroll
-          for (int j = 0; j < 8; ++j) v[j] = tab[(a.off_r[1] + 32 * kc + 8 * g + j) * CP + 16 * t + n] * w1[t];
-          const typename Pol::Frag aw = Pol::make(v);
-          Pol::mma(acc1[t][0], aw, bs[0]);
-          Pol::mma(acc1[t][1], aw, bs[1]);
+          const typename Pol::Frag aw = FS::get(frg, NT * (1 + NOUT) + 2 * t + kc, lane);
+          Pol::mma(u1[t][0], aw, bs[0]);
+          Pol::mma(u1[t][1], aw, bs[1]);
         }
       }
-      // the next step's staging writes must not overtake these reads
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-      __builtin_amdgcn_wave_barrier();
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      // acc1 += W^(1)[o, c] (Omega^(1)_0^T S), row c of the product = 16 t + out_row(g, r)
+#pragma unroll
+      for (int t = 0; t < NT; ++t)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const float w = outer_weight(z, 1, -1, 16 * t + Pol::out_row(g, r));
+          acc1[t][0][r] += w * u1[t][0][r];
+          acc1[t][1][r] += w * u1[t][1][r];
+        }
     }
   };
 
@@ -392,13 +448,14 @@ __global__ __launch_bounds__(512) void fused_sketch_kernel(FusedArgs a) {
   }
   // outer modes: the waves' accumulator rows, summed in wave order
 #pragma unroll
-  for (int k = 0; k < kMaxDims - 2; ++k) {
+  for (int k = 0; k < NOUT; ++k) {
     const int ms = k + 2;
-    if (k >= a.n_out || !((a.want >> ms) & 1)) continue;
+    if (!((a.want >> ms) & 1)) continue;
     const int lm = a.ell[ms];
     // partial index: (row block, i1 block, box coordinates other than k)
     int64_t pbox = 0, mul = 1;
-    for (int kk = 0; kk < a.n_out; ++kk) {
+#pragma unroll
+    for (int kk = 0; kk < NOUT; ++kk) {
       if (kk == k) continue;
       pbox += bc[kk] * mul;
       mul *= a.nbox[kk];
@@ -417,8 +474,8 @@ __global__ __launch_bounds__(512) void fused_sketch_kernel(FusedArgs a) {
 
 size_t round256(size_t v) { return (v + 255) / 256 * 256; }
 
-template <int P>
-hipError_t fused_go(int nt, const FusedArgs& a, dim3 grid, size_t lds, hipStream_t st) {
+template <int P, int NOUT>
+hipError_t fused_go_nout(int nt, const FusedArgs& a, dim3 grid, size_t lds, hipStream_t st) {
   auto pick = [&](auto kern) -> hipError_t {
     hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
@@ -426,10 +483,20 @@ hipError_t fused_go(int nt, const FusedArgs& a, dim3 grid, size_t lds, hipStream
     return hipGetLastError();
   };
   switch (nt) {
-    case 1: return pick(fused_sketch_kernel<P, 1>);
-    case 2: return pick(fused_sketch_kernel<P, 2>);
-    case 3: return pick(fused_sketch_kernel<P, 3>);
-    default: return pick(fused_sketch_kernel<P, 4>);
+    case 1: return pick(fused_sketch_kernel<P, 1, NOUT>);
+    case 2: return pick(fused_sketch_kernel<P, 2, NOUT>);
+    case 3: return pick(fused_sketch_kernel<P, 3, NOUT>);
+    default: return pick(fused_sketch_kernel<P, 4, NOUT>);
+  }
+}
+
+template <int P>
+hipError_t fused_go(int nt, const FusedArgs& a, dim3 grid, size_t lds, hipStream_t st) {
+  switch (a.n_out) {
+    case 1: return fused_go_nout<P, 1>(nt, a, grid, lds, st);
+    case 2: return fused_go_nout<P, 2>(nt, a, grid, lds, st);
+    case 3: return fused_go_nout<P, 3>(nt, a, grid, lds, st);
+    default: return hipErrorInvalidValue;
   }
 }
 
@@ -443,6 +510,7 @@ FusedPlan plan_fused(const SketchProblem* pbs, int nmodes) {
   FusedPlan fp{};
   fp.ok = false;
   if (nmodes < 2) return fp;
+  if (pbs[0].d < 3 || pbs[0].d > 5) return fp;  // one to three outer modes
   const SketchProblem& p0 = pbs[0];
   const int d = p0.d;
   if (p0.x_is_double || p0.prec == kFP64) return fp;
@@ -525,10 +593,12 @@ FusedPlan plan_fused(const SketchProblem* pbs, int nmodes) {
     a.nseg = ns;
     a.tab_rows = rows;
     a.acc_rows = acc_rows;
-    const size_t tab = (size_t)rows * cp * 4;
+    const size_t tab = (size_t)rows * (cp + 1) * 4;                       // pitch cp + 1
+    const size_t frag = (size_t)nt * (3 + n_out) * 64 * 32;               // static fragments
     const size_t stage = want1 ? (size_t)kFuWaves * 32 * kStagePitch * 4 : 0;
     const size_t red = (size_t)std::max(4 * nt, 2 * nt) * 4 * 64 * sizeof(double);  // end-of-kernel wave sums
-    a.stage_off = (int)((tab + 15) / 16 * 16);
+    a.frag_off = (int)((tab + 15) / 16 * 16);
+    a.stage_off = (int)(a.frag_off + frag);
     a.acc_off = (int)(a.stage_off + (std::max(stage, red) + 15) / 16 * 16);
     return (size_t)a.acc_off + (size_t)kFuWaves * acc_rows * cp * 4;
   };
