@@ -158,8 +158,8 @@ int krp_sthosvd(const void* X, int dtype, int d, const int64_t* dims, const int3
  *          ell_l = 0 selects ceil(1.5 ell_r); ell_r <= m s_b and ell_r <= n s_b
  *   m, n   block sizes, 1..64
  *   limit  the correlation of an instance keeps its length-(2 s_b - 1) sequence
- *          in 150 KiB of LDS: s_b up to about 12,700 blocks for fp32 data and
- *          6,300 for fp64 (larger values return KRP_EINVAL)
+ *          in the 160 KiB of LDS of a workgroup: s_b up to about 13,000 blocks
+ *          for fp32 data and 6,500 for fp64 (larger values return KRP_EINVAL)
  *   opts->prec  must be KRP_P_FP32 for fp32 data and KRP_P_FP64 for fp64 data:
  *          the sketch runs in the storage precision, the small dense algebra
  *          (Cholesky, least squares, eigenvectors) in fp64
@@ -168,7 +168,11 @@ int krp_sthosvd(const void* X, int dtype, int d, const int64_t* dims, const int3
  *   S      device, batch * r elements (descending per instance)
  *   V      device, sum_b n s_b r elements: V_b (n s_b) x r column-major
  * Each singular pair is sign-normalised: the entry of largest magnitude of
- * every column of U_b is positive. */
+ * every column of U_b is positive.  Status: an instance whose sketch Y_b is
+ * (numerically) rank-deficient takes the shifted CholeskyQR3 fallback
+ * (KRP_STAT_CHOL_SHIFT in opts->status_dev); one with no range at all (e.g. all
+ * blocks zero) returns KRP_ECHOL with zero U_b, S_b, V_b; a non-finite block
+ * returns KRP_ENONFINITE.  Other instances are unaffected. */
 int krp_hankel_lowrank(int batch, const int64_t* s, int m, int n, const void* h, int dtype, int r,
                        int ell_r, int ell_l, const krp_opts* opts, void* U, void* S, void* V,
                        void* stream);

@@ -17,6 +17,7 @@
 // CholeskyQR3).  Since diag(R) > 0 the result equals the Householder Q whose
 // R has a positive diagonal.
 #include "device_common.h"
+#include "elim.h"
 #include "kernels.h"
 
 namespace krp {
@@ -28,20 +29,14 @@ constexpr int kQrWaves = 8;
 constexpr int kQrThreads = 64 * kQrWaves;
 constexpr int kQrCh = 64;                 // rows per streamed chunk
 constexpr int kQrPitch = kQrMaxEll + 1;   // pitch of chunks, G and R^{-1}
-// Pivot rows of the elimination: 8 chunks of 16 columns, chunk stride 18
-// (the chunks start on distinct LDS banks).
-constexpr int kQrCPitch = 8 * 18;
-__device__ __forceinline__ int cpos(int c) { return (c >> 4) * 18 + (c & 15); }
 constexpr int kQrMaxTasks = 16;           // matrix-core tasks (<= 2 per wave)
 constexpr int kQrSplitMinChunks = 4;      // row chunks below which the split form is not used
 
 struct QrShared {
   double chunk_in[kQrCh * kQrPitch];   // rows of the streamed matrix (row-major); Gram partials at the end
   double chunk_out[kQrCh * kQrPitch];  // rows of the product with R^{-1} (row-major)
-  __align__(16) double c[2 * kQrCPitch];  // pivot rows of the elimination (by step parity)
-  double diag_u[kQrMaxEll];            // U[i][i] of the elimination
+  ElimShared es;                        // elimination scratch
   double g[kQrMaxEll * kQrPitch];      // Gram matrix; after a successful elimination R^{-1}
-  double diag_ref[kQrMaxEll];
   double tr;
 };
 
@@ -222,114 +217,8 @@ __device__ void qr_stream(const double* src, double* dst, int64_t n, int ell, vo
   }
 }
 
-// R^{-1} of G + shift I into sh.g by symmetric elimination of the rows of
-// [I | G] (width 2 ell).  Every row takes the full update
-//   row_i -= (U[k][i] / U[k][k]) row_k   for i > k
-// at step k: the identity part of row k is zero beyond column k and the part
-// of row i left of its diagonal is never read, so no column masks are needed.
-// All eight waves take part (lane = 8 rows x 8 column chunks of 16 per
-// wave): a lane owns one row x 16 columns in registers, and only the pivot
-// row of the next step goes through LDS.  Columns past 2 ell carry values
-// that are never used, so no step needs a per-column predicate.
-// Returns false (uniformly) on a pivot breakdown, leaving sh.g untouched.
-constexpr int kElimLanes = 512;
-constexpr int kElimMaxR = 1;   // rows per lane
-constexpr int kElimMaxC = 16;  // columns per lane (8 chunks cover 2 ell <= 128)
-
-__device__ bool qr_elim(int ell, double shift, QrShared& sh) {
-  const int tid = threadIdx.x;
-  const int width = 2 * ell;
-  constexpr int R = 1;
-  constexpr int C = kElimMaxC;
-  const bool part = tid < kElimLanes;
-  const int grp = tid / 8, ch = tid % 8;
-  const int r0 = grp * R, c0 = ch * C;
-  double cv[kElimMaxR][kElimMaxC];
-  __syncthreads();  // a previous elimination may still be reading sh.c
-  // combined row i: columns 0..ell-1 hold L^{-1}[i][.] (identity at first),
-  // columns ell..2 ell - 1 hold the Schur complement row U[i][.]
-#pragma unroll
-  for (int r = 0; r < kElimMaxR; ++r) {
-    const int i = r0 + r;
-#pragma unroll
-    for (int q = 0; q < kElimMaxC; ++q) {
-      const int c = c0 + q;
-      double v = 0.0;
-      if (part && r < R && i < ell && c < width) {
-        if (c < ell) v = (c == i) ? 1.0 : 0.0;
-        else v = sh.g[i * kQrPitch + c - ell] + ((c - ell == i) ? shift : 0.0);
-        if (i == 0) sh.c[cpos(c)] = v;  // the first pivot row
-      }
-      cv[r][q] = v;
-    }
-  }
-  if (tid < ell) sh.diag_ref[tid] = sh.g[tid * kQrPitch + tid] + shift;
-  __syncthreads();
-  // No early exit: a breakdown is recorded and tested after the loop (the
-  // remaining steps then run on non-finite values that are discarded), and
-  // the updates cover the whole register block unconditionally (multiplier 0
-  // for rows not below the pivot; columns past the block's width are never
-  // stored), which keeps every step free of divergent branches.
-  bool ok = true;
-  for (int k = 0; k < ell; ++k) {
-    const double* ck = &sh.c[(k & 1) * kQrCPitch];
-    const double piv = ck[cpos(ell + k)], ref = sh.diag_ref[k];
-    ok = ok && (piv > 1e-14 * ref) && isfinite(piv);
-    if (part) {
-      double rk[kElimMaxC], num[kElimMaxR];
-#pragma unroll
-      for (int q = 0; q < kElimMaxC; q += 2) {
-        const double2 t = *reinterpret_cast<const double2*>(&ck[ch * 18 + q]);
-        rk[q] = t.x;
-        rk[q + 1] = t.y;
-      }
-#pragma unroll
-      for (int r = 0; r < kElimMaxR; ++r) num[r] = ck[cpos(ell + min(r0 + r, ell - 1))];
-      const double rp = 1.0 / piv;
-#pragma unroll
-      for (int r = 0; r < kElimMaxR; ++r) {
-        const double l = (r0 + r > k && r0 + r < ell) ? num[r] * rp : 0.0;
-#pragma unroll
-        for (int q = 0; q < kElimMaxC; ++q) cv[r][q] -= l * rk[q];
-      }
-      // the next pivot row is final now
-      const int rn = k + 1 - r0;
-      if (rn >= 0 && rn < R && k + 1 < ell) {
-        double* cn = &sh.c[((k + 1) & 1) * kQrCPitch + ch * 18];
-#pragma unroll
-        for (int q = 0; q < kElimMaxC; q += 2) {
-          *reinterpret_cast<double2*>(&cn[q]) = make_double2(cv[0][q], cv[0][q + 1]);
-        }
-      }
-    }
-    if (tid == 0) sh.diag_u[k] = piv;
-    __syncthreads();
-  }
-  if (!ok) return false;
-  // R^{-1}[m][i] = L^{-1}[i][m] / sqrt(U[i][i]) for m <= i, zero elsewhere
-  // (including the padding up to the next multiple of 16)
-  if (part) {
-#pragma unroll
-    for (int r = 0; r < kElimMaxR; ++r) {
-      const int i = r0 + r;
-      if (r < R && i < ell) {
-        const double dinv = 1.0 / sqrt(sh.diag_u[i]);
-#pragma unroll
-        for (int q = 0; q < kElimMaxC; ++q) {
-          const int m = c0 + q;
-          if (q < C && m <= i) sh.g[m * kQrPitch + i] = cv[r][q] * dinv;
-        }
-      }
-    }
-  }
-  const int lp = (ell + 15) / 16 * 16;
-  for (int e = tid; e < lp * lp; e += kQrThreads) {
-    const int m = e / lp, i = e % lp;
-    if (m > i || i >= ell) sh.g[m * kQrPitch + i] = 0.0;
-  }
-  __syncthreads();
-  return true;
-}
+// R^{-1} of G + shift I into sh.g (see chol_inv_elim).
+__device__ bool qr_elim(int ell, double shift, QrShared& sh) { return chol_inv_elim(ell, shift, sh.g, sh.es); }
 
 // The whole CholeskyQR2 (with the shifted CholeskyQR3 fallback) of one matrix
 // on one workgroup: src (n x ell) -> dst (fp64) and qo (storage type).

@@ -6,39 +6,61 @@
 // matrices):
 //   Y[(a, al), c] = sum_{c'} Omega1[c', c] P_{a+c'}[al, c],  P_k = h_k Omega2
 //   Z[(c', be), j] = sum_a Psi1[a, j] R_{a+c'}[be, j],       R_k = h_k^T Psi2
-// so each output column is a correlation of a length-s filter (a column of
-// Omega1 or Psi1) with a length-(2s-1) sequence of small products; H is never
-// formed.  A workgroup owns one (instance, side, column chunk, row chunk) item:
-// it draws its factor columns, forms the P (or R) sequence in LDS and runs the
-// correlation with an 8x8 register window.  Items are issued longest-first
-// (instances ordered by decreasing s), so the hardware dispatcher balances the
-// uneven instances like an LPT schedule.
-// Completion (steps 3-7): CholeskyQR2 of Y (batched), M = Psi^T Q by the KRP
-// structure, W = M^+ Z^T by normal equations on the small M, the Gram matrix
-// W W^T, its Jacobi eigenvectors U_W, and U = Q U_W, S = sqrt(eig),
-// V = W^T U_W S^{-1}, with each singular pair sign-normalised.
+// For one output column this is a product with a banded Toeplitz matrix,
+// out[a] = sum_k F[a][k] P[k] with F[a][k] = f[k - a], which runs on the
+// matrix cores (16x16x4 fp32 or fp64 MFMA): the A operand is read straight
+// from the filter f (F's entries depend on k - a only), the B operand from the
+// P sequence, and the 16 columns of a tile hold the rows of P (block rows)
+// times output shifts of 16 rows.  H is never formed.
+//
+// One persistent launch does the sketches: workgroups pull (instance, side,
+// column, block-row chunk) items from an atomic counter in longest-first
+// order (instances by decreasing s), so the uneven instances are balanced
+// like an LPT schedule.
+//
+// Completion (steps 3-7), batched over all instances by row chunks so that a
+// large instance is spread over many workgroups:
+//   CholeskyQR of Y without forming Q: every pass sums the Gram matrix of the
+//   rows y R_cum^{-1} over the chunks, and a per-instance kernel factors it
+//   (shifted on a breakdown: shifted CholeskyQR3) and updates R_cum^{-1};
+//   two consecutive unshifted passes end the iteration.  Q = Y R_cum^{-1}.
+//   M = Psi^T Q = (Psi^T Y) R_cum^{-1}, with Psi^T Y summed in the first pass
+//   from the KRP rows of Psi; M^+ = R_M^{-1} Q_M^T from a CholeskyQR2 of M;
+//   W W^T = M^+ (Z^T Z) M^+^T (Z^T Z summed in the first pass) and its
+//   Jacobi eigenvectors U_W; U = Y (R_cum^{-1} U_W), S = sqrt(eig),
+//   V = W^T U_W S^{-1} = Z (M^+^T U_W S^{-1}); each singular pair is
+//   sign-normalised by the largest-magnitude entry of its column of U.
 #include "device_common.h"
+#include "elim.h"
 #include "hankel.h"
 #include "kernels.h"
 #include "philox.h"
 #include "truncate.h"
 
 #include <algorithm>
+#include <mutex>
 
 namespace krp {
 
 namespace {
 
 constexpr int kSetupThreads = 512;
-constexpr int kSketchThreads = 256;
-constexpr int kLsThreads = 512;
+constexpr int kSkThreads = 256;     // sketch workgroup: four waves
+constexpr int kSkGroup = 4;         // row tiles per wave held in accumulators
+constexpr int kChThreads = 256;     // completion chunk kernels: one thread per chunk row
+constexpr int kSub = 64;            // rows per staged sub-block of a chunk
+constexpr int kSP = kHankelMaxEll + 1;  // pitch of staged rows (doubles)
+constexpr int kStDone = 8, kStFail = 16;  // instance state bits (low bits: clean passes)
+
+static_assert(kChThreads == kHankelChRows, "one thread per chunk row");
 
 struct SetupArgs {
   int32_t s[kHankelGroup];
   int batch, m, n, ell_r, ell_l, r;
 };
 
-// Per-instance offsets (exclusive prefix sums) and the longest-first order.
+// Per-instance offsets (exclusive prefix sums), the longest-first order, the
+// chunk table, cleared pass states and the cleared work counter.
 __global__ __launch_bounds__(kSetupThreads) void hankel_setup_kernel(SetupArgs a, HankelTables t) {
   __shared__ int64_t sh[kHankelGroup];
   const int b = threadIdx.x;
@@ -57,17 +79,22 @@ __global__ __launch_bounds__(kSetupThreads) void hankel_setup_kernel(SetupArgs a
       }
     }
     __syncthreads();
-    if (b < B) out[b] = sh[b];
+    const int64_t r = b < B ? sh[b] : 0;
+    if (b < B) out[b] = r;
+    return r;
   };
+  const int64_t mx = a.m > a.n ? a.m : a.n;
+  const int64_t nch = (mx * s + kHankelChRows - 1) / kHankelChRows;
   scan((2 * s - 1) * a.m * a.n, t.h_off);
   scan(a.m * s * a.ell_r, t.y_off);
   scan(a.n * s * a.ell_l, t.z_off);
-  scan((int64_t)a.ell_r * a.n * s, t.w_off);
   scan(a.m * s * a.r, t.u_off);
   scan(a.n * s * a.r, t.v_off);
+  const int64_t c0 = scan(nch, t.ch_off);
   if (b < B) {
     t.s[b] = s;
-    t.y_rows[b] = a.m * s;
+    t.state[b] = 0;
+    for (int64_t c = 0; c < nch; ++c) t.chunk_inst[c0 + c] = b;
     int rank = 0;
     for (int i = 0; i < B; ++i) {
       const int64_t si = a.s[i];
@@ -75,383 +102,797 @@ __global__ __launch_bounds__(kSetupThreads) void hankel_setup_kernel(SetupArgs a
     }
     t.order[rank] = b;
   }
+  if (b == 0) *t.queue = 0;
 }
 
+// ---------------------------------------------------------------------------
+// Sketch: persistent workgroups over (instance, side, column, row chunk).
+// ---------------------------------------------------------------------------
 struct SketchArgsH {
   const void* h;
   HankelTables t;
-  double* y64;
-  double* z64;
+  void* y;
+  void* z;
   int m, n, ell_r, ell_l;
-  int nc[2], nrho[2];     // columns / rows per item for side 0 (Y) and 1 (Z)
-  int cchunks[2], rchunks[2];
-  int items_per_inst, items_side0;
+  int rp[2], hs[2], ach[2];
+  int items_side0, ipi, total;
+  int fl_cap, kp_cap;
   uint64_t seed, w2_base;
 };
 
 template <typename T>
-__global__ __launch_bounds__(kSketchThreads) void hankel_sketch_kernel(SketchArgsH a) {
+struct MmaT;
+template <>
+struct MmaT<float> {
+  using Acc = floatx4;
+  __device__ static Acc mma(float a, float b, Acc c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+  __device__ static int out_row(int g, int r) { return 4 * g + r; }
+};
+template <>
+struct MmaT<double> {
+  using Acc = doublex4;
+  __device__ static Acc mma(double a, double b, Acc c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  __device__ static int out_row(int g, int r) { return 4 * r + g; }
+};
+
+template <typename T>
+__global__ __launch_bounds__(kSkThreads) void hankel_sketch_kernel(SketchArgsH a) {
+  using M = MmaT<T>;
+  using Acc = typename M::Acc;
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  T* sm = reinterpret_cast<T*>(smem_raw);
-  const int q = blockIdx.x / a.items_per_inst;
-  int loc = blockIdx.x - q * a.items_per_inst;
-  const int b = a.t.order[q];
-  const int side = loc >= a.items_side0 ? 1 : 0;
-  if (side) loc -= a.items_side0;
-  const int cchunk = loc % a.cchunks[side];
-  const int rchunk = loc / a.cchunks[side];
-  const int nc_full = a.nc[side];
-  const int ell = side ? a.ell_l : a.ell_r;
-  const int c0 = cchunk * nc_full;
-  const int nc = min(nc_full, ell - c0);
-  const int R = side ? a.n : a.m;   // output rows per block
-  const int I = side ? a.m : a.n;   // contracted rows of the inner factor
-  const int rho0 = rchunk * a.nrho[side];
-  const int nr = min(a.nrho[side], R - rho0);
-  const int64_t s = a.t.s[b];
-  const int64_t K = 2 * s - 1;
-  const int64_t s_pad = (s + 7) / 8 * 8;
-  const int fid_filter = side ? 2 : 0, fid_inner = side ? 3 : 1;
+  T* filt = reinterpret_cast<T*>(smem_raw);  // filt[x + 16] = f[x], zero outside [0, s)
+  T* wv = filt + a.fl_cap;                   // the inner factor column (<= 64 entries)
+  T* P = wv + kHankelMaxBlock;               // P[k][rr], kp_cap x rp
+  __shared__ int item_sh;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int n16 = lane & 15, g = lane >> 4;
+  for (;;) {
+    __syncthreads();  // the previous item's LDS reads are done
+    if (tid == 0) item_sh = atomicAdd(a.t.queue, 1);
+    __syncthreads();
+    const int item = item_sh;
+    if (item >= a.total) break;
+    const int q = item / a.ipi;
+    int loc = item - q * a.ipi;
+    const int b = a.t.order[q];
+    const int side = loc >= a.items_side0 ? 1 : 0;
+    if (side) loc -= a.items_side0;
+    const int achs = a.ach[side];
+    const int c = loc / achs;
+    const int ac = loc - c * achs;
+    const int Rp = a.rp[side], H = a.hs[side];
+    const int R = side ? a.n : a.m;  // rows of a block of the output
+    const int I = side ? a.m : a.n;  // contracted block dimension
+    const int r0 = ac * Rp;
+    const int nr = min(Rp, R - r0);
+    const int s = (int)a.t.s[b];
+    const int kend = (s + 15 + 3) / 4 * 4;  // a row tile reduces over k < s + 15
+    const int ntiles = (s + 16 * H - 1) / (16 * H);
+    const int kp_rows = 16 * H * ntiles + kend;
+    const uint64_t fid_filter = side ? 2 : 0, fid_inner = side ? 3 : 1;
 
-  // LDS: P[k][rho][cc] (k < K + 16), filter[c'][cc] (c' < s_pad + 8), inner[i][cc]
-  T* P = sm;
-  T* filt = P + (K + 16) * nr * nc;
-  T* fin = filt + (s_pad + 8) * nc;
-  const int tid = threadIdx.x;
-  for (int e = tid; e < I * nc; e += kSketchThreads) {
-    const int i = e / nc, cc = e - (e / nc) * nc;
-    fin[e] = (T)gauss_entry(a.seed, a.w2_base | (uint64_t)fid_inner, (uint64_t)b, i, c0 + cc);
-  }
-  for (int64_t e = tid; e < (s_pad + 8) * nc; e += kSketchThreads) {
-    const int64_t r = e / nc;
-    const int cc = (int)(e - r * nc);
-    filt[e] = r < s ? (T)gauss_entry(a.seed, a.w2_base | (uint64_t)fid_filter, (uint64_t)b, r, c0 + cc)
-                    : (T)0;
-  }
-  __syncthreads();
-  const T* hb = reinterpret_cast<const T*>(a.h) + a.t.h_off[b];
-  const int64_t mn = (int64_t)a.m * a.n;
-  for (int64_t e = tid; e < (K + 16) * nr * nc; e += kSketchThreads) {
-    const int64_t k = e / (nr * nc);
-    const int rem = (int)(e - k * nr * nc);
-    const int rr = rem / nc, cc = rem - (rem / nc) * nc;
-    T v = (T)0;
-    if (k < K) {
-      const T* hk = hb + k * mn;
-      const int rho = rho0 + rr;
-      for (int i = 0; i < I; ++i) {
-        const T hv = side ? hk[i + (int64_t)a.m * rho] : hk[rho + (int64_t)a.m * i];
-        v += hv * fin[i * nc + cc];
+    for (int e = tid; e < kend + 16; e += kSkThreads) {
+      const int x = e - 16;
+      filt[e] = (x >= 0 && x < s) ? (T)gauss_entry(a.seed, a.w2_base | fid_filter, (uint64_t)b, x, c) : (T)0;
+    }
+    for (int e = tid; e < I; e += kSkThreads)
+      wv[e] = (T)gauss_entry(a.seed, a.w2_base | fid_inner, (uint64_t)b, e, c);
+    __syncthreads();
+    // P[k][rr] = sum_i h_k[r0 + rr, i] w[i] (side 0), sum_i h_k[i, r0 + rr] w[i] (side 1)
+    const T* hb = reinterpret_cast<const T*>(a.h) + a.t.h_off[b];
+    const int64_t mn = (int64_t)a.m * a.n;
+    const int K = 2 * s - 1;
+    const int64_t stride_i = side ? 1 : a.m;
+    const int64_t stride_r = side ? a.m : 1;
+    for (int e = tid; e < kp_rows * Rp; e += kSkThreads) {
+      const int k = e / Rp, rr = e - (e / Rp) * Rp;
+      T v = (T)0;
+      if (k < K && rr < nr) {
+        const T* hk = hb + (int64_t)k * mn + (int64_t)(r0 + rr) * stride_r;
+        for (int i = 0; i < I; ++i) v += hk[i * stride_i] * wv[i];
       }
+      P[e] = v;
     }
-    P[e] = v;
-  }
-  __syncthreads();
+    __syncthreads();
 
-  // Correlation: out[a, rho, c] = sum_{c'} filt[c'] P[a + c', rho], 8 outputs per task.
-  double* out = side ? a.z64 + a.t.z_off[b] : a.y64 + a.t.y_off[b];
-  const int64_t rows_out = (int64_t)R * s;
-  const int64_t nblk = s_pad / 8;
-  const int64_t tasks = nblk * nr * nc;
-  const int stride_k = nr * nc;
-  for (int64_t task = tid; task < tasks; task += kSketchThreads) {
-    const int rc = (int)(task % (nr * nc));
-    const int64_t blk = task / (nr * nc);
-    const int rr = rc / nc, cc = rc - (rc / nc) * nc;
-    const int64_t a0 = blk * 8;
-    T acc[8];
+    // Row tiles: tile t holds output rows a = 16 H t + i + 16 hh (i < 16 the
+    // tile row, column n16 = hh Rp + rr).  Columns past H Rp read a valid
+    // address and are not stored.
+    const int hh = min(n16 / Rp, H - 1);
+    const int rr = n16 - (n16 / Rp) * Rp;
+    const bool col_ok = n16 < H * Rp && rr < nr;
+    T* out = reinterpret_cast<T*>(side ? a.z : a.y) + (side ? a.t.z_off[b] : a.t.y_off[b]);
+    const int64_t rows_out = (int64_t)R * s;
+    for (int tb = wave; tb < ntiles; tb += 4 * kSkGroup) {
+      Acc acc[kSkGroup];
+      int prow[kSkGroup];
 #pragma unroll
-    for (int i = 0; i < 8; ++i) acc[i] = (T)0;
-    const T* pp = P + a0 * stride_k + rc;
-    const T* ff = filt + cc;
-    for (int64_t c8 = 0; c8 < s_pad; c8 += 8) {
-      T w[8], win[16];
+      for (int u = 0; u < kSkGroup; ++u) {
+        acc[u] = Acc{};
+        const int t = min(tb + 4 * u, ntiles - 1);
+        prow[u] = (16 * H * t + 16 * hh + g) * Rp + rr;
+      }
+      const T* fa = filt + 16 + g - n16;
+#pragma unroll 4
+      for (int k0 = 0; k0 < kend; k0 += 4) {
+        const T av = fa[k0];
 #pragma unroll
-      for (int j = 0; j < 8; ++j) w[j] = ff[(c8 + j) * nc];
+        for (int u = 0; u < kSkGroup; ++u) acc[u] = M::mma(av, P[prow[u] + k0 * Rp], acc[u]);
+      }
 #pragma unroll
-      for (int t2 = 0; t2 < 16; ++t2) win[t2] = pp[(c8 + t2) * stride_k];
+      for (int u = 0; u < kSkGroup; ++u) {
+        const int t = tb + 4 * u;
+        if (t >= ntiles || !col_ok) continue;
 #pragma unroll
-      for (int j = 0; j < 8; ++j)
-#pragma unroll
-        for (int i = 0; i < 8; ++i) acc[i] += w[j] * win[i + j];
-    }
-#pragma unroll
-    for (int i = 0; i < 8; ++i) {
-      const int64_t aa = a0 + i;
-      if (aa < s) out[aa * R + rho0 + rr + rows_out * (c0 + cc)] = (double)acc[i];
+        for (int r = 0; r < 4; ++r) {
+          const int arow = 16 * H * t + M::out_row(g, r) + 16 * hh;
+          if (arow < s) out[(int64_t)arow * R + r0 + rr + rows_out * c] = acc[u][r];
+        }
+      }
     }
   }
 }
 
-// Per instance: M = Psi^T Q (ell_l x ell_r), the Cholesky factor of M^T M,
-// W = (M^T M)^{-1} M^T Z^T (ell_r x n s) and G_W = W W^T (ell_r x ell_r).
-struct LsArgs {
+// ---------------------------------------------------------------------------
+// Completion: Gram passes over row chunks.
+// ---------------------------------------------------------------------------
+struct ChunkArgs {
   HankelTables t;
-  const double* q64;
-  const double* z64;
-  double* w64;
-  double* gw;
-  int* status;
+  const void* y;
+  const void* z;
+  double* part;        // per chunk partial matrices
+  const double* rinv;  // per instance R_cum^{-1} (ell_r x ell_r, row-major)
   int m, n, ell_r, ell_l;
+  int part_stride;
   uint64_t seed, w2_base;
 };
 
-__global__ __launch_bounds__(kLsThreads) void hankel_ls_kernel(LsArgs a) {
-  constexpr int L = kHankelMaxEll;
-  __shared__ double Mx[L * L];                // M, column-major ell_l x ell_r
-  __shared__ double C[L * L];                 // M^T M, then its Cholesky R (upper)
-  __shared__ double Gm[L * L];                // (M^T M)^{-1} M^T, ell_r x ell_l
-  __shared__ double psi2[kHankelMaxBlock * L];  // m x ell_l
-  __shared__ double qch[32 * L];              // 32 rows of Q (or columns of W) [row][j]
-  __shared__ double psi1[34 * L];             // Psi1 rows of the chunk
-  __shared__ int fail;
+__device__ __forceinline__ int tri_count(int T) { return T * (T + 1) / 2; }
+__device__ __forceinline__ void tri_pair(int T, int p, int& i, int& j) {
+  i = 0;
+  while (p >= T - i) {
+    p -= T - i;
+    ++i;
+  }
+  j = i + p;
+}
+
+// Gram-type MFMA tile over one staged sub-block: acc += X[:, 16 ti..]^T X'[:, 16 tj..]
+// (rows of the sub-block, pitch kSP).
+__device__ __forceinline__ void gram_tile(doublex4& acc, const double* X, int ti, const double* Xp, int tj, int n16,
+                                          int g) {
+#pragma unroll 4
+  for (int k0 = 0; k0 < kSub; k0 += 4) {
+    const double av = X[(k0 + g) * kSP + 16 * ti + n16];
+    const double bv = Xp[(k0 + g) * kSP + 16 * tj + n16];
+    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
+  }
+}
+
+// Stages rows [row0, row0 + kSub) of an (nrows x cols) column-major matrix
+// into LDS (row-major, pitch kSP, zero past nrows and for columns in
+// [cols, cpad)).
+template <typename T>
+__device__ __forceinline__ void stage_rows(const T* src, int64_t nrows, int cols, int cpad, int64_t row0,
+                                           double* dst) {
+  for (int e = threadIdx.x; e < kSub * cpad; e += kChThreads) {
+    const int c = e / kSub, rl = e - (e / kSub) * kSub;
+    const int64_t row = row0 + rl;
+    dst[rl * kSP + c] = (c < cols && row < nrows) ? (double)src[row + nrows * c] : 0.0;
+  }
+}
+
+// Pass 1: partial G_Y = Y^T Y, T = Psi^T Y and G_Z = Z^T Z of one chunk.
+// Passes after the first: partial Gram matrix of the rows Y R_cum^{-1}.
+template <typename T, bool FIRST>
+__global__ __launch_bounds__(kChThreads) void hankel_gram_kernel(ChunkArgs a) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  double* xs = reinterpret_cast<double*>(smem_raw);  // kSub x kSP: rows of Y (or Z)
+  double* ps = xs + kSub * kSP;                       // kSub x kSP: rows of Psi, or of Y R^{-1}
+  double* aux = ps + kSub * kSP;                      // FIRST: Psi2 (m x ell_l); else R^{-1} (kSP x kSP)
+  const int ch = blockIdx.x;
+  const int b = a.t.chunk_inst[ch];
+  if (!FIRST && (a.t.state[b] & (kStDone | kStFail))) return;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int n16 = lane & 15, g = lane >> 4;
+  const int64_t s = a.t.s[b];
+  const int64_t cl = ch - a.t.ch_off[b];
+  const int lr = a.ell_r, ll = a.ell_l;
+  const int TR = (lr + 15) / 16, TL = (ll + 15) / 16;
+  const int64_t ny = (int64_t)a.m * s, nz = (int64_t)a.n * s;
+  const int64_t r_lo = cl * kHankelChRows;
+  const T* Y = reinterpret_cast<const T*>(a.y) + a.t.y_off[b];
+  const T* Z = reinterpret_cast<const T*>(a.z) + a.t.z_off[b];
+  double* part = a.part + (int64_t)ch * a.part_stride;
+
+  if (FIRST) {
+    const int nq = (ll + 3) / 4;
+    for (int e = tid; e < a.m * nq; e += kChThreads) {
+      const int al = e / nq, jq = e - (e / nq) * nq;
+      double gq[4];
+      gauss_quad(a.seed, a.w2_base | 3ull, (uint64_t)b, al, jq, gq);
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if (4 * jq + u < ll) aux[al * kSP + 4 * jq + u] = gq[u];
+    }
+  } else {
+    const double* rc = a.rinv + (int64_t)b * lr * lr;
+    for (int e = tid; e < 16 * TR * 16 * TR; e += kChThreads) {
+      const int i = e / (16 * TR), j = e - (e / (16 * TR)) * (16 * TR);
+      aux[i * kSP + j] = (i < lr && j < lr) ? rc[i * lr + j] : 0.0;
+    }
+  }
+  // tiles: Y phase (pass 1: G_Y pairs then T tiles; later: G pairs)
+  const int ny_tiles = tri_count(TR) + (FIRST ? TL * TR : 0);
+  doublex4 acc[4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) acc[u] = doublex4{0.0, 0.0, 0.0, 0.0};
+  const int64_t y_hi = min(r_lo + kHankelChRows, ny);
+  for (int64_t row0 = r_lo; row0 < y_hi; row0 += kSub) {
+    __syncthreads();
+    stage_rows<T>(Y, ny, lr, 16 * TR, row0, xs);
+    if (FIRST) {
+      // Psi rows (a, al): Psi1[a, j] Psi2[al, j]; Psi1 by quads of columns
+      const int nq = (ll + 3) / 4;
+      const int64_t a_lo = row0 / a.m;
+      const int64_t a_hi = min((row0 + kSub - 1) / a.m, s - 1);
+      for (int e = tid; e < (int)(a_hi - a_lo + 1) * nq; e += kChThreads) {
+        const int ar = e / nq, jq = e - (e / nq) * nq;
+        const int64_t aa = a_lo + ar;
+        double gq[4];
+        gauss_quad(a.seed, a.w2_base | 2ull, (uint64_t)b, aa, jq, gq);
+        for (int al = 0; al < a.m; ++al) {
+          const int64_t rl = aa * a.m + al - row0;
+          if (rl < 0 || rl >= kSub || aa * a.m + al >= ny) continue;
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const int j = 4 * jq + u;
+            if (j < ll) ps[rl * kSP + j] = gq[u] * aux[al * kSP + j];
+          }
+        }
+      }
+      // zero: Psi columns past ell_l (up to the tile padding) and rows past
+      // the end of Y (the generation above leaves both untouched)
+      for (int e = tid; e < kSub * 16 * TL; e += kChThreads) {
+        const int rl = e / (16 * TL), j = e - (e / (16 * TL)) * (16 * TL);
+        if (j >= ll || row0 + rl >= ny) ps[rl * kSP + j] = 0.0;
+      }
+    }
+    __syncthreads();
+    if (!FIRST) {
+      // q = y R^{-1} for the sub-block: 4 row tiles x TR column tiles
+      for (int tile = wave; tile < 4 * TR; tile += 4) {
+        const int rt = tile & 3, tc = tile >> 2;
+        doublex4 q = doublex4{0.0, 0.0, 0.0, 0.0};
+        for (int k0 = 0; k0 < 16 * tc + 16; k0 += 4) {
+          const double av = xs[(16 * rt + n16) * kSP + k0 + g];
+          const double bv = aux[(k0 + g) * kSP + 16 * tc + n16];
+          q = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, q, 0, 0, 0);
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) ps[(16 * rt + 4 * r + g) * kSP + 16 * tc + n16] = q[r];
+      }
+      __syncthreads();
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int tile = wave + 4 * u;
+      if (tile < ny_tiles) {
+        if (tile < tri_count(TR)) {
+          int ti, tj;
+          tri_pair(TR, tile, ti, tj);
+          const double* X = FIRST ? xs : ps;
+          gram_tile(acc[u], X, ti, X, tj, n16, g);
+        } else {
+          const int e = tile - tri_count(TR);
+          const int tl = e / TR, tr = e - (e / TR) * TR;
+          gram_tile(acc[u], ps, tl, xs, tr, n16, g);
+        }
+      }
+    }
+  }
+  // partial G (ell_r x ell_r, both triangles), T (ell_l x ell_r, column-major)
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int tile = wave + 4 * u;
+    if (tile >= ny_tiles) continue;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int ri = 4 * r + g, cj = n16;
+      if (tile < tri_count(TR)) {
+        int ti, tj;
+        tri_pair(TR, tile, ti, tj);
+        const int i = 16 * ti + ri, j = 16 * tj + cj;
+        if (i < lr && j < lr) {
+          part[i + lr * j] = acc[u][r];
+          part[j + lr * i] = acc[u][r];
+        }
+      } else {
+        const int e = tile - tri_count(TR);
+        const int tl = e / TR, tr = e - (e / TR) * TR;
+        const int i = 16 * tl + ri, j = 16 * tr + cj;
+        if (i < ll && j < lr) part[lr * lr + i + ll * j] = acc[u][r];
+      }
+    }
+  }
+  if (!FIRST) return;
+  // Z phase: G_Z pairs
+  const int nz_tiles = tri_count(TL);
+  doublex4 zacc[2];
+  zacc[0] = doublex4{0.0, 0.0, 0.0, 0.0};
+  zacc[1] = zacc[0];
+  const int64_t z_hi = min(r_lo + kHankelChRows, nz);
+  for (int64_t row0 = r_lo; row0 < z_hi; row0 += kSub) {
+    __syncthreads();
+    stage_rows<T>(Z, nz, ll, 16 * TL, row0, xs);
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int tile = wave + 4 * u;
+      if (tile < nz_tiles) {
+        int ti, tj;
+        tri_pair(TL, tile, ti, tj);
+        gram_tile(zacc[u], xs, ti, xs, tj, n16, g);
+      }
+    }
+  }
+  double* pz = part + lr * lr + ll * lr;
+#pragma unroll
+  for (int u = 0; u < 2; ++u) {
+    const int tile = wave + 4 * u;
+    if (tile >= nz_tiles) continue;
+    int ti, tj;
+    tri_pair(TL, tile, ti, tj);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int i = 16 * ti + 4 * r + g, j = 16 * tj + n16;
+      if (i < ll && j < ll) {
+        pz[i + ll * j] = zacc[u][r];
+        pz[j + ll * i] = zacc[u][r];
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Per-instance small kernels (512 threads: the elimination's workgroup).
+// ---------------------------------------------------------------------------
+struct SmallArgs {
+  HankelTables t;
+  const double* part;
+  int part_stride;
+  double* rinv;   // per instance R_cum^{-1}
+  double* tsum;   // per instance Psi^T Y (ell_l x ell_r)
+  double* gz;     // per instance Z^T Z
+  double* kmat;   // per instance W W^T (ell_r x ell_r)
+  double* mp;     // per instance M^+ (ell_r x ell_l, row-major)
+  int* status;
+  int m, n, ell_r, ell_l;
+  int pass, last;
+};
+
+struct SmallShared {
+  ElimShared es;
+  double g[kElimMaxEll * kElimPitch];
+  double red[kElimThreads / 64];
+  double tr;
+};
+
+__device__ double wg_trace(const double* g, int ell, SmallShared& sh) {
+  __syncthreads();
+  if (threadIdx.x < 64) {
+    const double d = threadIdx.x < ell ? g[threadIdx.x * kElimPitch + threadIdx.x] : 0.0;
+    const double t = wave_sum(d);
+    if (threadIdx.x == 0) sh.tr = t;
+  }
+  __syncthreads();
+  return sh.tr;
+}
+
+// One CholeskyQR pass of instance b: sums the chunk partials in chunk order,
+// factors (shifted on a breakdown), updates R_cum^{-1} and the pass state.
+__global__ __launch_bounds__(kElimThreads) void hankel_pass_kernel(SmallArgs a) {
+  __shared__ SmallShared sh;
+  __shared__ double rc[kHankelMaxEll * kHankelMaxEll];
+  const int b = blockIdx.x;
+  const int tid = threadIdx.x;
+  const int st0 = a.t.state[b];
+  if (st0 & (kStDone | kStFail)) return;
+  const int lr = a.ell_r, ll = a.ell_l;
+  const int64_t s = a.t.s[b];
+  const int64_t ch0 = a.t.ch_off[b];
+  const int64_t mx = a.m > a.n ? a.m : a.n;
+  const int nch = (int)((mx * s + kHankelChRows - 1) / kHankelChRows);
+  // chunk sums (fixed order)
+  const int nsum = a.pass == 1 ? lr * lr + ll * lr + ll * ll : lr * lr;
+  for (int e = tid; e < nsum; e += kElimThreads) {
+    double v = 0.0;
+    for (int c = 0; c < nch; ++c) v += a.part[(ch0 + c) * a.part_stride + e];
+    if (e < lr * lr) {
+      const int i = e % lr, j = e / lr;
+      sh.g[i * kElimPitch + j] = v;
+    } else if (e < lr * lr + ll * lr) {
+      a.tsum[(int64_t)b * ll * lr + e - lr * lr] = v;
+    } else {
+      a.gz[(int64_t)b * ll * ll + e - lr * lr - ll * lr] = v;
+    }
+  }
+  if (a.pass > 1)
+    for (int e = tid; e < lr * lr; e += kElimThreads) rc[e] = a.rinv[(int64_t)b * lr * lr + e];
+  __syncthreads();
+  double tr = wg_trace(sh.g, lr, sh);
+  if (a.pass == 1) {
+    // the Z side must be finite too
+    double zt = 0.0;
+    if (tid < 64) {
+      for (int i = tid; i < ll; i += 64) zt += a.gz[(int64_t)b * ll * ll + i + ll * i];
+      zt = wave_sum(zt);
+      if (tid == 0) sh.red[0] = zt;
+    }
+    __syncthreads();
+    if (!isfinite(sh.red[0])) tr = sh.red[0];
+  }
+  if (!isfinite(tr)) {
+    if (tid == 0) {
+      raise_status(a.status, kStatNonFinite);
+      a.t.state[b] = kStFail;
+    }
+    return;
+  }
+  int clean = st0 & 3;
+  if (chol_inv_elim(lr, 0.0, sh.g, sh.es)) {
+    ++clean;
+  } else {
+    if (tid == 0) raise_status(a.status, kStatCholShift);
+    const double shift = 11.0 * ((double)a.m * s * lr + (double)lr * (lr + 1)) * 0x1.0p-53 * tr;
+    if (!chol_inv_elim(lr, shift, sh.g, sh.es)) {
+      if (tid == 0) {
+        raise_status(a.status, kStatCholFail);
+        a.t.state[b] = kStFail;
+      }
+      return;
+    }
+    clean = 0;
+  }
+  // R_cum^{-1} <- R_cum^{-1} R_p^{-1} (both upper triangular)
+  double* out = a.rinv + (int64_t)b * lr * lr;
+  for (int e = tid; e < lr * lr; e += kElimThreads) {
+    const int i = e / lr, j = e - (e / lr) * lr;
+    double v = 0.0;
+    if (a.pass == 1) {
+      v = sh.g[i * kElimPitch + j];
+    } else if (i <= j) {
+      for (int k = i; k <= j; ++k) v += rc[i * lr + k] * sh.g[k * kElimPitch + j];
+    }
+    out[e] = v;
+  }
+  if (tid == 0) {
+    int st = clean;
+    if (clean >= 2) st = kStDone;
+    else if (a.pass == a.last) {
+      raise_status(a.status, kStatCholFail);
+      st = kStFail;
+    }
+    a.t.state[b] = st;
+  }
+}
+
+// M = (Psi^T Y) R_cum^{-1}; M = Q_M R_M by CholeskyQR2; M^+ = R_M^{-1} Q_M^T;
+// K = M^+ (Z^T Z) M^+^T for the eigensolver.  A failed instance gets K = 0.
+__global__ __launch_bounds__(kElimThreads) void hankel_solve_kernel(SmallArgs a) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  __shared__ SmallShared sh;
   const int b = blockIdx.x;
   const int tid = threadIdx.x;
   const int lr = a.ell_r, ll = a.ell_l;
-  const int64_t s = a.t.s[b];
-  const int64_t nrow = (int64_t)a.m * s;
-  const double* Q = a.q64 + a.t.y_off[b];
-  const int nq = (ll + 3) >> 2;  // generator calls per factor row (four columns each)
-  for (int e = tid; e < a.m * nq; e += kLsThreads) {
-    const int al = e / nq, jq = e - (e / nq) * nq;
-    double g[4];
-    gauss_quad(a.seed, a.w2_base | 3ull, (uint64_t)b, al, jq, g);
-#pragma unroll
-    for (int u = 0; u < 4; ++u)
-      if (4 * jq + u < ll) psi2[al * ll + 4 * jq + u] = g[u];
-  }
-  constexpr int kU = (L * L + kLsThreads - 1) / kLsThreads;
-  double acc[kU];
-#pragma unroll
-  for (int u = 0; u < kU; ++u) acc[u] = 0.0;
-  for (int64_t t0 = 0; t0 < nrow; t0 += 32) {
-    const int rc = (int)min<int64_t>(32, nrow - t0);
-    const int64_t a_lo = t0 / a.m;
-    const int64_t a_hi = (t0 + rc - 1) / a.m;
-    __syncthreads();
-    for (int e = tid; e < 32 * lr; e += kLsThreads) {
-      const int r = e / lr, j = e - (e / lr) * lr;
-      qch[e] = r < rc ? Q[t0 + r + nrow * j] : 0.0;
-    }
-    for (int e = tid; e < (int)(a_hi - a_lo + 1) * nq; e += kLsThreads) {
-      const int r = e / nq, jq = e - (e / nq) * nq;
-      double g[4];
-      gauss_quad(a.seed, a.w2_base | 2ull, (uint64_t)b, a_lo + r, jq, g);
-#pragma unroll
-      for (int u = 0; u < 4; ++u)
-        if (4 * jq + u < ll) psi1[r * ll + 4 * jq + u] = g[u];
-    }
-    __syncthreads();
-#pragma unroll
-    for (int u = 0; u < kU; ++u) {
-      const int p = tid + u * kLsThreads;
-      if (p < ll * lr) {
-        const int c = p % ll, j = p / ll;
-        double sum = acc[u];
-        for (int r = 0; r < rc; ++r) {
-          const int64_t t = t0 + r;
-          const int64_t aa = t / a.m;
-          const int al = (int)(t - aa * a.m);
-          sum += psi1[(aa - a_lo) * ll + c] * psi2[al * ll + c] * qch[r * lr + j];
-        }
-        acc[u] = sum;
-      }
-    }
-  }
-#pragma unroll
-  for (int u = 0; u < kU; ++u) {
-    const int p = tid + u * kLsThreads;
-    if (p < ll * lr) Mx[p] = acc[u];  // p = c + ll * j
-  }
-  if (tid == 0) fail = 0;
-  __syncthreads();
-  for (int p = tid; p < lr * lr; p += kLsThreads) {
-    const int i = p % lr, j = p / lr;
-    double sum = 0.0;
-    for (int c = 0; c < ll; ++c) sum += Mx[c + ll * i] * Mx[c + ll * j];
-    C[i + L * j] = sum;
-  }
-  __syncthreads();
-  // Cholesky M^T M = R^T R, R upper in C[i + L j] (i <= j)
-  for (int k = 0; k < lr; ++k) {
-    if (tid == 0) {
-      const double d = C[k + L * k];
-      if (!(d > 0.0) || !isfinite(d)) fail = 1;
-      else C[k + L * k] = sqrt(d);
-    }
-    __syncthreads();
-    if (fail) break;
-    const double rkk = C[k + L * k];
-    for (int j = k + 1 + tid; j < lr; j += kLsThreads) C[k + L * j] /= rkk;
-    __syncthreads();
-    const int mm = lr - k - 1;
-    for (int e = tid; e < mm * mm; e += kLsThreads) {
-      const int i = k + 1 + e / mm, j = k + 1 + e % mm;
-      if (i <= j) C[i + L * j] -= C[k + L * i] * C[k + L * j];
-    }
-    __syncthreads();
-  }
-  if (fail) {
-    if (tid == 0) raise_status(a.status, kStatCholFail);
+  double* kout = a.kmat + (int64_t)b * lr * lr;
+  double* mp_out = a.mp + (int64_t)b * lr * ll;
+  if (a.t.state[b] & kStFail) {
+    for (int e = tid; e < lr * lr; e += kElimThreads) kout[e] = 0.0;
+    for (int e = tid; e < lr * ll; e += kElimThreads) mp_out[e] = 0.0;
     return;
   }
-  // Gm[:, c] = R^{-1} R^{-T} M[c, :]^T, one thread per c (solution kept in LDS)
-  if (tid < ll) {
-    const int c = tid;
-    for (int j = 0; j < lr; ++j) {
-      double v = Mx[c + ll * j];
-      for (int k = 0; k < j; ++k) v -= C[k + L * j] * Gm[k + lr * c];
-      Gm[j + lr * c] = v / C[j + L * j];
-    }
-    for (int j = lr - 1; j >= 0; --j) {
-      double v = Gm[j + lr * c];
-      for (int k = j + 1; k < lr; ++k) v -= C[j + L * k] * Gm[k + lr * c];
-      Gm[j + lr * c] = v / C[j + L * j];
-    }
+  const int LS = kHankelMaxEll * kHankelMaxEll;
+  double* rc = reinterpret_cast<double*>(smem_raw);  // R_cum^{-1}, later R_M^{-1} (lr x lr)
+  double* mx = rc + LS;                              // M, later Q_M (ll x lr, row-major)
+  double* qa = mx + LS;                              // Q_a (ll x lr)
+  double* ra = qa + LS;                              // R_a^{-1} (lr x lr)
+  double* mpl = ra + LS;                             // M^+ (lr x ll)
+  const double* ts = a.tsum + (int64_t)b * ll * lr;
+  for (int e = tid; e < lr * lr; e += kElimThreads) rc[e] = a.rinv[(int64_t)b * lr * lr + e];
+  __syncthreads();
+  for (int e = tid; e < ll * lr; e += kElimThreads) {
+    const int j = e / lr, i = e - (e / lr) * lr;  // M[j][i]
+    double v = 0.0;
+    for (int k = 0; k <= i; ++k) v += ts[j + ll * k] * rc[k * lr + i];
+    mx[e] = v;
   }
   __syncthreads();
-  // W[j, col] = sum_c Gm[j, c] Z[col, c]
-  const int64_t ncol = (int64_t)a.n * s;
-  const double* Z = a.z64 + a.t.z_off[b];
-  double* W = a.w64 + a.t.w_off[b];
-  for (int64_t e = tid; e < ncol * lr; e += kLsThreads) {
-    const int j = (int)(e % lr);
-    const int64_t col = e / lr;
-    double sum = 0.0;
-    for (int c = 0; c < ll; ++c) sum += Gm[j + lr * c] * Z[col + ncol * c];
-    W[e] = sum;
-  }
-  __syncthreads();
-  // G_W = W W^T, chunks of 32 columns of W staged in LDS
-#pragma unroll
-  for (int u = 0; u < kU; ++u) acc[u] = 0.0;
-  for (int64_t c0 = 0; c0 < ncol; c0 += 32) {
-    const int cc = (int)min<int64_t>(32, ncol - c0);
-    __syncthreads();
-    for (int e = tid; e < 32 * lr; e += kLsThreads) {
-      const int r = e / lr, j = e - (e / lr) * lr;
-      qch[e] = r < cc ? W[j + (int64_t)lr * (c0 + r)] : 0.0;
+  // two CholeskyQR passes on M (ll x lr)
+  const double* src = mx;
+  for (int pass = 0; pass < 2; ++pass) {
+    for (int e = tid; e < lr * lr; e += kElimThreads) {
+      const int i = e / lr, j = e - (e / lr) * lr;
+      double v = 0.0;
+      for (int k = 0; k < ll; ++k) v += src[k * lr + i] * src[k * lr + j];
+      sh.g[i * kElimPitch + j] = v;
     }
     __syncthreads();
-#pragma unroll
-    for (int u = 0; u < kU; ++u) {
-      const int p = tid + u * kLsThreads;
-      if (p < lr * lr) {
-        const int i = p % lr, j = p / lr;
-        double sum = acc[u];
-        for (int r = 0; r < 32; ++r) sum += qch[r * lr + i] * qch[r * lr + j];
-        acc[u] = sum;
+    if (!chol_inv_elim(lr, 0.0, sh.g, sh.es)) {
+      if (tid == 0) {
+        raise_status(a.status, kStatCholFail);
+        a.t.state[b] = kStFail;
+      }
+      for (int e = tid; e < lr * lr; e += kElimThreads) kout[e] = 0.0;
+      for (int e = tid; e < lr * ll; e += kElimThreads) mp_out[e] = 0.0;
+      return;
+    }
+    double* dst = pass == 0 ? qa : mx;
+    for (int e = tid; e < ll * lr; e += kElimThreads) {
+      const int j = e / lr, i = e - (e / lr) * lr;
+      double v = 0.0;
+      for (int k = 0; k <= i; ++k) v += src[j * lr + k] * sh.g[k * kElimPitch + i];
+      dst[e] = v;
+    }
+    if (pass == 0) {
+      for (int e = tid; e < lr * lr; e += kElimThreads) ra[e] = sh.g[(e / lr) * kElimPitch + e % lr];
+    } else {
+      // R_M^{-1} = R_a^{-1} R_b^{-1}
+      for (int e = tid; e < lr * lr; e += kElimThreads) {
+        const int i = e / lr, j = e - (e / lr) * lr;
+        double v = 0.0;
+        for (int k = i; k <= j; ++k) v += ra[i * lr + k] * sh.g[k * kElimPitch + j];
+        rc[e] = i <= j ? v : 0.0;
       }
     }
+    __syncthreads();
+    src = qa;
   }
-  double* gw = a.gw + (int64_t)b * lr * lr;
-#pragma unroll
-  for (int u = 0; u < kU; ++u) {
-    const int p = tid + u * kLsThreads;
-    if (p < lr * lr) gw[p] = acc[u];
+  // M^+ = R_M^{-1} Q_M^T (lr x ll), Q_M in mx
+  for (int e = tid; e < lr * ll; e += kElimThreads) {
+    const int i = e / ll, j = e - (e / ll) * ll;
+    double v = 0.0;
+    for (int k = i; k < lr; ++k) v += rc[i * lr + k] * mx[j * lr + k];
+    mpl[e] = v;
+    mp_out[e] = v;
+  }
+  __syncthreads();
+  // Tmp = M^+ G_Z (lr x ll) into qa; K = Tmp M^+^T (symmetrised)
+  const double* gz = a.gz + (int64_t)b * ll * ll;
+  for (int e = tid; e < lr * ll; e += kElimThreads) {
+    const int i = e / ll, j = e - (e / ll) * ll;
+    double v = 0.0;
+    for (int k = 0; k < ll; ++k) v += mpl[i * ll + k] * gz[k + ll * j];
+    qa[e] = v;
+  }
+  __syncthreads();
+  for (int e = tid; e < lr * lr; e += kElimThreads) {
+    const int i = e / lr, j = e - (e / lr) * lr;
+    double v = 0.0, w = 0.0;
+    for (int k = 0; k < ll; ++k) {
+      v += qa[i * ll + k] * mpl[j * ll + k];
+      w += qa[j * ll + k] * mpl[i * ll + k];
+    }
+    kout[i + lr * j] = 0.5 * (v + w);
   }
 }
 
-// U = Q U_W, S = sqrt(eig), V = W^T U_W S^{-1}; columns sign-normalised so that
-// the largest-magnitude entry of each column of U is positive.
-struct FinishArgs {
+// B_U = R_cum^{-1} U_W (ell_r x r), S = sqrt(eig), B_V = M^+^T U_W S^{-1}
+// (ell_l x r); a failed instance gets zeros.
+struct PostArgs {
   HankelTables t;
-  const double* q64;
-  const double* w64;
-  const double* uw;   // batch x (ell_r x r)
-  const double* ev;   // batch x r
-  void* U;
+  const double* rinv;
+  const double* mp;
+  const double* uw;
+  const double* ev;
+  double* bu;
+  double* bv;
   void* S;
-  void* V;
   int out_double;
-  int m, n, ell_r, r;
+  int ell_r, ell_l, r;
 };
 
-__global__ __launch_bounds__(kLsThreads) void hankel_finish_kernel(FinishArgs a) {
-  __shared__ double uw[kHankelMaxEll * kHankelMaxEll];
-  __shared__ double sgn[kHankelMaxEll];
-  __shared__ double redv[kLsThreads / 64];
-  __shared__ int64_t redi[kLsThreads / 64];
+__global__ __launch_bounds__(256) void hankel_post_kernel(PostArgs a) {
   const int b = blockIdx.x;
-  const int tid = threadIdx.x;
+  const int lr = a.ell_r, ll = a.ell_l, r = a.r;
+  const bool fail = (a.t.state[b] & kStFail) != 0;
+  const double* rc = a.rinv + (int64_t)b * lr * lr;
+  const double* mp = a.mp + (int64_t)b * lr * ll;
+  const double* uw = a.uw + (int64_t)b * lr * r;
+  const double* ev = a.ev + (int64_t)b * r;
+  for (int e = threadIdx.x; e < lr * r; e += blockDim.x) {
+    const int i = e % lr, j = e / lr;
+    double v = 0.0;
+    if (!fail)
+      for (int k = i; k < lr; ++k) v += rc[i * lr + k] * uw[k + lr * j];
+    a.bu[(int64_t)b * lr * r + e] = v;
+  }
+  for (int e = threadIdx.x; e < ll * r; e += blockDim.x) {
+    const int i = e % ll, j = e / ll;
+    const double sig = sqrt(fmax(ev[j], 0.0));
+    double v = 0.0;
+    if (!fail && sig > 0.0) {
+      for (int k = 0; k < lr; ++k) v += mp[k * ll + i] * uw[k + lr * j];
+      v /= sig;
+    }
+    a.bv[(int64_t)b * ll * r + e] = v;
+  }
+  for (int j = threadIdx.x; j < r; j += blockDim.x) {
+    const double sig = fail ? 0.0 : sqrt(fmax(ev[j], 0.0));
+    if (a.out_double) reinterpret_cast<double*>(a.S)[(int64_t)b * r + j] = sig;
+    else reinterpret_cast<float*>(a.S)[(int64_t)b * r + j] = (float)sig;
+  }
+}
+
+// Rows of U = Y B_U of one chunk: per column, the largest magnitude (first
+// row on ties) and its signed value.
+struct FinArgs {
+  HankelTables t;
+  const void* y;
+  const void* z;
+  const double* bu;
+  const double* bv;
+  double* am;  // per chunk x r: (|u|, row, u)
+  void* U;
+  void* V;
+  int out_double;
+  int m, n, ell_r, ell_l, r;
+};
+
+template <typename T>
+__global__ __launch_bounds__(kChThreads) void hankel_argmax_kernel(FinArgs a) {
+  __shared__ double bu[kHankelMaxEll * kHankelMaxEll];
+  __shared__ double rv[kChThreads / 64][kHankelMaxEll];
+  __shared__ double ru[kChThreads / 64][kHankelMaxEll];
+  __shared__ int64_t ri[kChThreads / 64][kHankelMaxEll];
+  const int ch = blockIdx.x;
+  const int b = a.t.chunk_inst[ch];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int lr = a.ell_r, r = a.r;
   const int64_t s = a.t.s[b];
-  const int64_t nrow = (int64_t)a.m * s;
-  const int64_t ncol = (int64_t)a.n * s;
-  const double* Q = a.q64 + a.t.y_off[b];
-  const double* W = a.w64 + a.t.w_off[b];
-  for (int e = tid; e < lr * r; e += kLsThreads) uw[e] = a.uw[(int64_t)b * lr * r + e];
+  const int64_t ny = (int64_t)a.m * s;
+  const int64_t row = (ch - a.t.ch_off[b]) * kHankelChRows + tid;
+  for (int e = tid; e < lr * r; e += kChThreads) bu[e] = a.bu[(int64_t)b * lr * r + e];
   __syncthreads();
+  const T* Y = reinterpret_cast<const T*>(a.y) + a.t.y_off[b];
+  double yv[kHankelMaxEll];
+  const bool valid = row < ny;
+#pragma unroll
+  for (int k = 0; k < kHankelMaxEll; ++k) yv[k] = (valid && k < lr) ? (double)Y[row + ny * k] : 0.0;
   for (int j = 0; j < r; ++j) {
-    double best = -1.0;
-    int64_t bi = 0;
-    for (int64_t t = tid; t < nrow; t += kLsThreads) {
-      double u = 0.0;
-      for (int i = 0; i < lr; ++i) u += Q[t + nrow * i] * uw[i + lr * j];
-      const double au = fabs(u);
-      if (au > best) {
-        best = au;
-        bi = t;
-      }
-    }
-    // wave reduction of (value, index): larger value, then smaller index
+    double u = 0.0;
+#pragma unroll
+    for (int k = 0; k < kHankelMaxEll; ++k)
+      if (k < lr) u += yv[k] * bu[k + lr * j];
+    double best = valid ? fabs(u) : -1.0;
+    int64_t bi = valid ? row : INT64_MAX;
+    double bu_v = u;
     for (int off = 32; off >= 1; off >>= 1) {
       const double ov = __shfl_xor(best, off, 64);
       const int64_t oi = __shfl_xor(bi, off, 64);
+      const double ou = __shfl_xor(bu_v, off, 64);
       if (ov > best || (ov == best && oi < bi)) {
         best = ov;
         bi = oi;
+        bu_v = ou;
       }
     }
-    if ((tid & 63) == 0) {
-      redv[tid >> 6] = best;
-      redi[tid >> 6] = bi;
+    if (lane == 0) {
+      rv[wave][j] = best;
+      ri[wave][j] = bi;
+      ru[wave][j] = bu_v;
     }
-    __syncthreads();
-    if (tid == 0) {
-      double bv = redv[0];
-      int64_t bix = redi[0];
-      for (int w = 1; w < kLsThreads / 64; ++w)
-        if (redv[w] > bv || (redv[w] == bv && redi[w] < bix)) {
-          bv = redv[w];
-          bix = redi[w];
-        }
-      double u = 0.0;
-      for (int i = 0; i < lr; ++i) u += Q[bix + nrow * i] * uw[i + lr * j];
-      sgn[j] = u < 0.0 ? -1.0 : 1.0;
-    }
-    __syncthreads();
   }
-  for (int64_t e = tid; e < nrow * r; e += kLsThreads) {
-    const int64_t t = e % nrow;
-    const int j = (int)(e / nrow);
-    double u = 0.0;
-    for (int i = 0; i < lr; ++i) u += Q[t + nrow * i] * uw[i + lr * j];
-    u *= sgn[j];
-    const int64_t o = a.t.u_off[b] + e;
-    if (a.out_double) reinterpret_cast<double*>(a.U)[o] = u;
-    else reinterpret_cast<float*>(a.U)[o] = (float)u;
-  }
-  for (int64_t e = tid; e < ncol * r; e += kLsThreads) {
-    const int64_t col = e % ncol;
-    const int j = (int)(e / ncol);
-    const double sig = sqrt(fmax(a.ev[(int64_t)b * r + j], 0.0));
-    double v = 0.0;
-    for (int i = 0; i < lr; ++i) v += W[i + (int64_t)lr * col] * uw[i + lr * j];
-    v = sig > 0.0 ? sgn[j] * v / sig : 0.0;
-    const int64_t o = a.t.v_off[b] + e;
-    if (a.out_double) reinterpret_cast<double*>(a.V)[o] = v;
-    else reinterpret_cast<float*>(a.V)[o] = (float)v;
-  }
-  for (int j = tid; j < r; j += kLsThreads) {
-    const double sig = sqrt(fmax(a.ev[(int64_t)b * r + j], 0.0));
-    const int64_t o = (int64_t)b * r + j;
-    if (a.out_double) reinterpret_cast<double*>(a.S)[o] = sig;
-    else reinterpret_cast<float*>(a.S)[o] = (float)sig;
+  __syncthreads();
+  for (int j = tid; j < r; j += kChThreads) {
+    double best = rv[0][j], bu_v = ru[0][j];
+    int64_t bi = ri[0][j];
+    for (int w = 1; w < kChThreads / 64; ++w)
+      if (rv[w][j] > best || (rv[w][j] == best && ri[w][j] < bi)) {
+        best = rv[w][j];
+        bi = ri[w][j];
+        bu_v = ru[w][j];
+      }
+    double* o = a.am + ((int64_t)ch * r + j) * 3;
+    o[0] = best;
+    o[1] = (double)bi;
+    o[2] = bu_v;
   }
 }
 
+// Sign of each column from the argmax partials of the instance (chunk
+// order), then U = sgn (Y B_U) and V = sgn (Z B_V) for the rows of the chunk.
+template <typename T>
+__global__ __launch_bounds__(kChThreads) void hankel_write_kernel(FinArgs a) {
+  __shared__ double bu[kHankelMaxEll * kHankelMaxEll];
+  __shared__ double bv[kHankelMaxEll * kHankelMaxEll];
+  __shared__ double sgn[kHankelMaxEll];
+  const int ch = blockIdx.x;
+  const int b = a.t.chunk_inst[ch];
+  const int tid = threadIdx.x;
+  const int lr = a.ell_r, ll = a.ell_l, r = a.r;
+  const int64_t s = a.t.s[b];
+  const int64_t ch0 = a.t.ch_off[b];
+  const int64_t mx = a.m > a.n ? a.m : a.n;
+  const int nch = (int)((mx * s + kHankelChRows - 1) / kHankelChRows);
+  for (int e = tid; e < lr * r; e += kChThreads) bu[e] = a.bu[(int64_t)b * lr * r + e];
+  for (int e = tid; e < ll * r; e += kChThreads) bv[e] = a.bv[(int64_t)b * ll * r + e];
+  for (int j = tid; j < r; j += kChThreads) {
+    double best = -2.0, bu_v = 0.0, bi = 0.0;
+    for (int c = 0; c < nch; ++c) {
+      const double* p = a.am + ((ch0 + c) * r + j) * 3;
+      if (p[0] > best || (p[0] == best && p[1] < bi)) {
+        best = p[0];
+        bi = p[1];
+        bu_v = p[2];
+      }
+    }
+    sgn[j] = bu_v < 0.0 ? -1.0 : 1.0;
+  }
+  __syncthreads();
+  const int64_t row = (ch - ch0) * kHankelChRows + tid;
+  const int64_t ny = (int64_t)a.m * s, nz = (int64_t)a.n * s;
+  if (row < ny) {
+    const T* Y = reinterpret_cast<const T*>(a.y) + a.t.y_off[b];
+    double yv[kHankelMaxEll];
+#pragma unroll
+    for (int k = 0; k < kHankelMaxEll; ++k) yv[k] = k < lr ? (double)Y[row + ny * k] : 0.0;
+    for (int j = 0; j < r; ++j) {
+      double u = 0.0;
+#pragma unroll
+      for (int k = 0; k < kHankelMaxEll; ++k)
+        if (k < lr) u += yv[k] * bu[k + lr * j];
+      u *= sgn[j];
+      const int64_t o = a.t.u_off[b] + row + ny * j;
+      if (a.out_double) reinterpret_cast<double*>(a.U)[o] = u;
+      else reinterpret_cast<float*>(a.U)[o] = (float)u;
+    }
+  }
+  if (row < nz) {
+    const T* Z = reinterpret_cast<const T*>(a.z) + a.t.z_off[b];
+    double zv[kHankelMaxEll];
+#pragma unroll
+    for (int k = 0; k < kHankelMaxEll; ++k) zv[k] = k < ll ? (double)Z[row + nz * k] : 0.0;
+    for (int j = 0; j < r; ++j) {
+      double v = 0.0;
+#pragma unroll
+      for (int k = 0; k < kHankelMaxEll; ++k)
+        if (k < ll) v += zv[k] * bv[k + ll * j];
+      v *= sgn[j];
+      const int64_t o = a.t.v_off[b] + row + nz * j;
+      if (a.out_double) reinterpret_cast<double*>(a.V)[o] = v;
+      else reinterpret_cast<float*>(a.V)[o] = (float)v;
+    }
+  }
+}
+
+size_t sketch_lds_bytes(int fl_cap, int kp_cap, int rp_max, size_t tsz) {
+  return ((size_t)fl_cap + kHankelMaxBlock + (size_t)kp_cap * rp_max) * tsz;
+}
+
+size_t gram_lds_bytes() { return (size_t)(2 * kSub * kSP + kHankelMaxBlock * kSP) * sizeof(double); }
+size_t solve_lds_bytes() { return (size_t)5 * kHankelMaxEll * kHankelMaxEll * sizeof(double); }
+
+int device_cus() {
+  static int cus = 0;
+  static std::once_flag once;
+  std::call_once(once, [] {
+    int dev = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
+      cus = prop.multiProcessorCount;
+    if (cus <= 0) cus = 256;
+  });
+  return cus;
+}
+
 }  // namespace
+
+// gfx950 gives a workgroup up to 160 KiB of LDS; the sketch keeps a little
+// for its static variables.
+size_t hankel_lds_limit() { return 160 * 1024 - 256; }
 
 HankelPlan plan_hankel(int batch, const int64_t* s, int m, int n, int r, int ell_r, int ell_l,
                        int is_double) {
@@ -463,34 +904,54 @@ HankelPlan plan_hankel(int batch, const int64_t* s, int m, int n, int r, int ell
   p.ell_r = ell_r;
   p.ell_l = ell_l;
   p.is_double = is_double;
-  int64_t smax = 1, ssum = 0;
+  int64_t smax = 1, ssum = 0, nch = 0;
+  const int64_t mx = std::max(m, n);
   for (int b = 0; b < batch; ++b) {
     smax = std::max<int64_t>(smax, s[b]);
     ssum += s[b];
+    nch += (mx * s[b] + kHankelChRows - 1) / kHankelChRows;
   }
   p.s_max = smax;
   p.s_sum = ssum;
+  p.n_chunks = (int)nch;
   const size_t tsz = is_double ? 8 : 4;
-  const size_t budget = 150 * 1024;
-  const int64_t s_pad = (smax + 7) / 8 * 8;
+  // Sketch items: the largest block-row chunk whose LDS fits 40 KB (four
+  // workgroups per CU), else the largest that fits the limit.
+  // extents for the largest instance (the kernel's own, per instance, are
+  // never larger): filter entries kend + 16, P rows 16 H ntiles + kend
+  const int kend_max = (int)((smax + 18) / 4 * 4);
+  p.fl_cap = kend_max + 16;
+  auto kp_rows = [&](int hs) { return (int)(16 * hs * ((smax + 16 * hs - 1) / (16 * hs)) + kend_max); };
   for (int side = 0; side < 2; ++side) {
-    const int R = side ? n : m, I = side ? m : n, ell = side ? ell_l : ell_r;
-    int nc = std::min(ell, is_double ? 2 : 3);
-    int nr = R;
-    auto lds = [&](int c, int rr) {
-      return ((size_t)(2 * smax - 1 + 16) * rr * c + (size_t)(s_pad + 8) * c + (size_t)I * c) * tsz;
-    };
-    while (nc > 1 && lds(nc, nr) > budget) --nc;
-    while (nr > 1 && lds(nc, nr) > budget) nr = (nr + 1) / 2;
-    p.nc[side] = nc;
-    p.nrho[side] = nr;
-    p.cchunks[side] = (ell + nc - 1) / nc;
-    p.rchunks[side] = (R + nr - 1) / nr;
-    p.lds[side] = lds(nc, nr);
+    const int R = side ? n : m;
+    int best = 0;
+    for (int pass = 0; pass < 2 && !best; ++pass) {
+      const size_t budget = pass == 0 ? 40 * 1024 : hankel_lds_limit();
+      for (int rp = std::min(R, 16); rp >= 1; --rp) {
+        const int hs = 16 / rp;
+        const int kp = kp_rows(hs);
+        if (sketch_lds_bytes(p.fl_cap, kp, rp, tsz) <= budget) {
+          best = rp;
+          break;
+        }
+      }
+    }
+    if (!best) best = 1;
+    p.rp[side] = best;
+    p.hs[side] = 16 / best;
+    p.ach[side] = (R + best - 1) / best;
   }
-  p.items_side0 = p.cchunks[0] * p.rchunks[0];
-  p.items_per_inst = p.items_side0 + p.cchunks[1] * p.rchunks[1];
-  p.lds_max = std::max(p.lds[0], p.lds[1]);
+  int kp = 0, rpm = 0;
+  for (int side = 0; side < 2; ++side) {
+    kp = std::max<int>(kp, kp_rows(p.hs[side]));
+    rpm = std::max(rpm, p.rp[side]);
+  }
+  p.kp_cap = kp;
+  p.sketch_lds = sketch_lds_bytes(p.fl_cap, kp, rpm, tsz);
+  p.items_side0 = ell_r * p.ach[0];
+  p.items_per_inst = p.items_side0 + ell_l * p.ach[1];
+  const int per_cu = (int)std::max<size_t>(1, std::min<size_t>(8, (160 * 1024) / std::max<size_t>(p.sketch_lds, 1)));
+  p.sketch_grid = (int)std::min<int64_t>((int64_t)device_cus() * per_cu, (int64_t)p.items_per_inst * batch);
   // workspace layout
   size_t off = 0;
   auto take = [&](size_t bytes) {
@@ -499,14 +960,21 @@ HankelPlan plan_hankel(int batch, const int64_t* s, int m, int n, int r, int ell
     return o;
   };
   const int64_t B = batch;
-  p.off_tab = take((size_t)B * 9 * 8 + 64);
-  p.off_y = take((size_t)m * ssum * ell_r * 8);
-  p.off_z = take((size_t)n * ssum * ell_l * 8);
-  p.off_w = take((size_t)ell_r * n * ssum * 8);
-  p.off_gw = take((size_t)B * ell_r * ell_r * 8);
-  p.off_uw = take((size_t)B * ell_r * r * 8);
+  const int lr = ell_r, ll = ell_l;
+  p.off_tab = take((size_t)B * 7 * 8 + (size_t)B * 4 * 2 + (size_t)nch * 4 + 64);
+  p.off_y = take((size_t)m * ssum * lr * 8);
+  p.off_z = take((size_t)n * ssum * ll * 8);
+  p.off_part = take((size_t)nch * (lr * lr + ll * lr + ll * ll) * 8);
+  p.off_rinv = take((size_t)B * lr * lr * 8);
+  p.off_t = take((size_t)B * ll * lr * 8);
+  p.off_gz = take((size_t)B * ll * ll * 8);
+  p.off_k = take((size_t)B * lr * lr * 8);
+  p.off_mp = take((size_t)B * lr * ll * 8);
+  p.off_uw = take((size_t)B * lr * r * 8);
   p.off_ev = take((size_t)B * r * 8);
-  p.off_status = take(64);
+  p.off_bu = take((size_t)B * lr * r * 8);
+  p.off_bv = take((size_t)B * ll * r * 8);
+  p.off_am = take((size_t)nch * r * 3 * 8);
   p.ws_bytes = off;
   return p;
 }
@@ -519,17 +987,21 @@ HankelTables hankel_tables(const HankelPlan& p, char* ws) {
   t.h_off = base + B;
   t.y_off = base + 2 * B;
   t.z_off = base + 3 * B;
-  t.w_off = base + 4 * B;
-  t.u_off = base + 5 * B;
-  t.v_off = base + 6 * B;
-  t.y_rows = base + 7 * B;
-  t.order = reinterpret_cast<int32_t*>(base + 8 * B);
+  t.u_off = base + 4 * B;
+  t.v_off = base + 5 * B;
+  t.ch_off = base + 6 * B;
+  int32_t* ib = reinterpret_cast<int32_t*>(base + 7 * B);
+  t.order = ib;
+  t.state = ib + B;
+  t.chunk_inst = ib + 2 * B;
+  t.queue = ib + 2 * B + p.n_chunks;
   return t;
 }
 
-hipError_t launch_hankel(const HankelPlan& p, const int64_t* s_host, const void* h, uint64_t seed,
-                         uint32_t draw, void* U, void* S, void* V, char* ws, int* status,
-                         hipStream_t st) {
+template <typename T>
+static hipError_t launch_typed(const HankelPlan& p, const int64_t* s_host, const void* h, uint64_t seed,
+                               uint32_t draw, void* U, void* S, void* V, char* ws, int* status,
+                               hipStream_t st) {
   const HankelTables t = hankel_tables(p, ws);
   SetupArgs sa{};
   for (int b = 0; b < p.batch; ++b) sa.s[b] = (int32_t)s_host[b];
@@ -542,86 +1014,137 @@ hipError_t launch_hankel(const HankelPlan& p, const int64_t* s_host, const void*
   hipLaunchKernelGGL(hankel_setup_kernel, dim3(1), dim3(kSetupThreads), 0, st, sa, t);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
+  const uint64_t w2 = counter_word2(draw, 0, 0);
+  void* y = ws + p.off_y;
+  void* z = ws + p.off_z;
 
-  double* y64 = reinterpret_cast<double*>(ws + p.off_y);
-  double* z64 = reinterpret_cast<double*>(ws + p.off_z);
   SketchArgsH ka{};
   ka.h = h;
   ka.t = t;
-  ka.y64 = y64;
-  ka.z64 = z64;
+  ka.y = y;
+  ka.z = z;
   ka.m = p.m;
   ka.n = p.n;
   ka.ell_r = p.ell_r;
   ka.ell_l = p.ell_l;
   for (int side = 0; side < 2; ++side) {
-    ka.nc[side] = p.nc[side];
-    ka.nrho[side] = p.nrho[side];
-    ka.cchunks[side] = p.cchunks[side];
-    ka.rchunks[side] = p.rchunks[side];
+    ka.rp[side] = p.rp[side];
+    ka.hs[side] = p.hs[side];
+    ka.ach[side] = p.ach[side];
   }
-  ka.items_per_inst = p.items_per_inst;
   ka.items_side0 = p.items_side0;
+  ka.ipi = p.items_per_inst;
+  ka.total = p.items_per_inst * p.batch;
+  ka.fl_cap = p.fl_cap;
+  ka.kp_cap = p.kp_cap;
   ka.seed = seed;
-  ka.w2_base = counter_word2(draw, 0, 0);
-  const unsigned grid = (unsigned)(p.items_per_inst * p.batch);
-  if (p.is_double) {
-    e = hipFuncSetAttribute((const void*)hankel_sketch_kernel<double>,
-                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)p.lds_max);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(hankel_sketch_kernel<double>, dim3(grid), dim3(kSketchThreads), p.lds_max, st, ka);
-  } else {
-    e = hipFuncSetAttribute((const void*)hankel_sketch_kernel<float>,
-                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)p.lds_max);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(hankel_sketch_kernel<float>, dim3(grid), dim3(kSketchThreads), p.lds_max, st, ka);
-  }
+  ka.w2_base = w2;
+  e = hipFuncSetAttribute((const void*)hankel_sketch_kernel<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                          (int)p.sketch_lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(hankel_sketch_kernel<T>, dim3(p.sketch_grid), dim3(kSkThreads), p.sketch_lds, st, ka);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
 
-  // Q of every Y (in place), batched CholeskyQR2
-  e = launch_cholqr(p.batch, 0, p.ell_r, y64, y64, nullptr, 0, t.y_off, t.y_rows, status, st);
+  double* part = reinterpret_cast<double*>(ws + p.off_part);
+  const int lr = p.ell_r, ll = p.ell_l;
+  ChunkArgs ca{};
+  ca.t = t;
+  ca.y = y;
+  ca.z = z;
+  ca.part = part;
+  ca.rinv = reinterpret_cast<double*>(ws + p.off_rinv);
+  ca.m = p.m;
+  ca.n = p.n;
+  ca.ell_r = lr;
+  ca.ell_l = ll;
+  ca.part_stride = lr * lr + ll * lr + ll * ll;
+  ca.seed = seed;
+  ca.w2_base = w2;
+  SmallArgs sm{};
+  sm.t = t;
+  sm.part = part;
+  sm.part_stride = ca.part_stride;
+  sm.rinv = reinterpret_cast<double*>(ws + p.off_rinv);
+  sm.tsum = reinterpret_cast<double*>(ws + p.off_t);
+  sm.gz = reinterpret_cast<double*>(ws + p.off_gz);
+  sm.kmat = reinterpret_cast<double*>(ws + p.off_k);
+  sm.mp = reinterpret_cast<double*>(ws + p.off_mp);
+  sm.status = status;
+  sm.m = p.m;
+  sm.n = p.n;
+  sm.ell_r = lr;
+  sm.ell_l = ll;
+  sm.last = kHankelPasses;
+  const size_t glds = gram_lds_bytes();
+  for (int pass = 1; pass <= kHankelPasses; ++pass) {
+    auto gk = pass == 1 ? hankel_gram_kernel<T, true> : hankel_gram_kernel<T, false>;
+    e = hipFuncSetAttribute((const void*)gk, hipFuncAttributeMaxDynamicSharedMemorySize, (int)glds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(gk, dim3(p.n_chunks), dim3(kChThreads), glds, st, ca);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    sm.pass = pass;
+    hipLaunchKernelGGL(hankel_pass_kernel, dim3(p.batch), dim3(kElimThreads), 0, st, sm);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  const size_t slds = solve_lds_bytes();
+  e = hipFuncSetAttribute((const void*)hankel_solve_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)slds);
   if (e != hipSuccess) return e;
-
-  LsArgs la{};
-  la.t = t;
-  la.q64 = y64;
-  la.z64 = z64;
-  la.w64 = reinterpret_cast<double*>(ws + p.off_w);
-  la.gw = reinterpret_cast<double*>(ws + p.off_gw);
-  la.status = status;
-  la.m = p.m;
-  la.n = p.n;
-  la.ell_r = p.ell_r;
-  la.ell_l = p.ell_l;
-  la.seed = seed;
-  la.w2_base = counter_word2(draw, 0, 0);
-  hipLaunchKernelGGL(hankel_ls_kernel, dim3(p.batch), dim3(kLsThreads), 0, st, la);
+  hipLaunchKernelGGL(hankel_solve_kernel, dim3(p.batch), dim3(kElimThreads), slds, st, sm);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
 
   double* uw = reinterpret_cast<double*>(ws + p.off_uw);
   double* ev = reinterpret_cast<double*>(ws + p.off_ev);
-  e = launch_sym_eig(p.batch, p.ell_r, p.r, la.gw, (int64_t)p.ell_r * p.ell_r, uw,
-                     (int64_t)p.ell_r * p.r, ev, p.r, st);
+  e = launch_sym_eig(p.batch, lr, p.r, sm.kmat, (int64_t)lr * lr, uw, (int64_t)lr * p.r, ev, p.r, st);
   if (e != hipSuccess) return e;
 
-  FinishArgs fa{};
+  PostArgs pa{};
+  pa.t = t;
+  pa.rinv = sm.rinv;
+  pa.mp = sm.mp;
+  pa.uw = uw;
+  pa.ev = ev;
+  pa.bu = reinterpret_cast<double*>(ws + p.off_bu);
+  pa.bv = reinterpret_cast<double*>(ws + p.off_bv);
+  pa.S = S;
+  pa.out_double = p.is_double;
+  pa.ell_r = lr;
+  pa.ell_l = ll;
+  pa.r = p.r;
+  hipLaunchKernelGGL(hankel_post_kernel, dim3(p.batch), dim3(256), 0, st, pa);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+
+  FinArgs fa{};
   fa.t = t;
-  fa.q64 = y64;
-  fa.w64 = la.w64;
-  fa.uw = uw;
-  fa.ev = ev;
+  fa.y = y;
+  fa.z = z;
+  fa.bu = pa.bu;
+  fa.bv = pa.bv;
+  fa.am = reinterpret_cast<double*>(ws + p.off_am);
   fa.U = U;
-  fa.S = S;
   fa.V = V;
   fa.out_double = p.is_double;
   fa.m = p.m;
   fa.n = p.n;
-  fa.ell_r = p.ell_r;
+  fa.ell_r = lr;
+  fa.ell_l = ll;
   fa.r = p.r;
-  hipLaunchKernelGGL(hankel_finish_kernel, dim3(p.batch), dim3(kLsThreads), 0, st, fa);
+  hipLaunchKernelGGL(hankel_argmax_kernel<T>, dim3(p.n_chunks), dim3(kChThreads), 0, st, fa);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(hankel_write_kernel<T>, dim3(p.n_chunks), dim3(kChThreads), 0, st, fa);
   return hipGetLastError();
+}
+
+hipError_t launch_hankel(const HankelPlan& p, const int64_t* s_host, const void* h, uint64_t seed,
+                         uint32_t draw, void* U, void* S, void* V, char* ws, int* status,
+                         hipStream_t st) {
+  if (p.is_double) return launch_typed<double>(p, s_host, h, seed, draw, U, S, V, ws, status, st);
+  return launch_typed<float>(p, s_host, h, seed, draw, U, S, V, ws, status, st);
 }
 
 }  // namespace krp

@@ -35,7 +35,7 @@ int plan_groups(int batch, const int64_t* s, int m, int n, int r, int ell_r, int
     g.v_off = v_off;
     g.s_off = (int64_t)first * r;
     g.plan = plan_hankel(g.count, s + first, m, n, r, ell_r, ell_l, is_double);
-    if (g.plan.lds_max > 150 * 1024)
+    if (g.plan.sketch_lds > hankel_lds_limit())
       return set_error(KRP_EINVAL, "block count s=%lld is too large for the LDS-resident sketch",
                        (long long)g.plan.s_max);
     g.ws_off = total;
