@@ -21,6 +21,8 @@ struct HankelTables {
   int64_t* u_off;   // U_b (m s x r) in the output
   int64_t* v_off;   // V_b (n s x r)
   int64_t* ch_off;  // first completion chunk of instance b
+  int64_t* p_off;   // P sequences of instance b (both sides) in the P buffer
+  int64_t* f_off;   // filter columns (Omega1, then Psi1) of instance b
   int32_t* order;   // instances by decreasing s (ties: lower index first)
   int32_t* chunk_inst;  // instance of each completion chunk
   int32_t* state;   // CholeskyQR pass state of each instance
@@ -38,7 +40,9 @@ struct HankelPlan {
   int fl_cap, kp_cap;
   size_t sketch_lds;
   int sketch_grid;
-  size_t off_tab, off_y, off_z, off_part, off_rinv, off_t, off_gz, off_k, off_mp, off_uw, off_ev, off_bu,
+  int pseq_kc, pseq_chunks;  // P-sequence kernel: blocks per workgroup, workgroups per instance
+  size_t pseq_lds;
+  size_t off_tab, off_pall, off_filt, off_y, off_z, off_part, off_rinv, off_t, off_gz, off_k, off_mp, off_uw, off_ev, off_bu,
       off_bv, off_am, ws_bytes;
 };
 

@@ -62,26 +62,28 @@ struct SetupArgs {
 // Per-instance offsets (exclusive prefix sums), the longest-first order, the
 // chunk table, cleared pass states and the cleared work counter.
 __global__ __launch_bounds__(kSetupThreads) void hankel_setup_kernel(SetupArgs a, HankelTables t) {
-  __shared__ int64_t sh[kHankelGroup];
-  const int b = threadIdx.x;
+  __shared__ int64_t wsum[kSetupThreads / 64];
+  __shared__ int32_t ss[kHankelGroup];
+  const int b = threadIdx.x, lane = b & 63, wave = b >> 6;
   const int B = a.batch;
   const int64_t s = b < B ? a.s[b] : 0;
+  ss[b] = (int32_t)s;
+  __syncthreads();
+  // exclusive prefix sum over the batch: wave scans, then the wave totals
   auto scan = [&](int64_t v, int64_t* out) {
-    __syncthreads();
-    if (b < kHankelGroup) sh[b] = v;
-    __syncthreads();
-    if (b == 0) {
-      int64_t acc = 0;
-      for (int i = 0; i < B; ++i) {
-        const int64_t x = sh[i];
-        sh[i] = acc;
-        acc += x;
-      }
+    long long x = v;
+    for (int off = 1; off < 64; off <<= 1) {
+      const long long y = __shfl_up(x, off, 64);
+      if (lane >= off) x += y;
     }
+    __syncthreads();  // the previous scan's totals are read
+    if (lane == 63) wsum[wave] = x;
     __syncthreads();
-    const int64_t r = b < B ? sh[b] : 0;
-    if (b < B) out[b] = r;
-    return r;
+    int64_t base = 0;
+    for (int w = 0; w < wave; ++w) base += wsum[w];
+    const int64_t excl = base + x - v;
+    if (b < B) out[b] = excl;
+    return excl;
   };
   const int64_t mx = a.m > a.n ? a.m : a.n;
   const int64_t nch = (mx * s + kHankelChRows - 1) / kHankelChRows;
@@ -90,26 +92,146 @@ __global__ __launch_bounds__(kSetupThreads) void hankel_setup_kernel(SetupArgs a
   scan(a.n * s * a.ell_l, t.z_off);
   scan(a.m * s * a.r, t.u_off);
   scan(a.n * s * a.r, t.v_off);
+  scan(s > 0 ? (2 * s - 1) * ((int64_t)a.m * a.ell_r + (int64_t)a.n * a.ell_l) : 0, t.p_off);
+  scan(s * (a.ell_r + a.ell_l), t.f_off);
   const int64_t c0 = scan(nch, t.ch_off);
   if (b < B) {
     t.s[b] = s;
     t.state[b] = 0;
     for (int64_t c = 0; c < nch; ++c) t.chunk_inst[c0 + c] = b;
+    // rank by decreasing s (ties: lower index first); eight entries per step
     int rank = 0;
-    for (int i = 0; i < B; ++i) {
-      const int64_t si = a.s[i];
-      if (si > s || (si == s && i < b)) ++rank;
+    for (int i0 = 0; i0 < B; i0 += 8) {
+      int32_t sv[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) sv[u] = ss[min(i0 + u, B - 1)];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int i = i0 + u;
+        rank += (i < B && (sv[u] > s || (sv[u] == s && i < b))) ? 1 : 0;
+      }
     }
     t.order[rank] = b;
   }
   if (b == 0) *t.queue = 0;
 }
 
+// P sequences of both sides for a run of blocks of one instance:
+//   side 0: P_k[al, c] = sum_be h_k[al, be] Omega2[be, c]   (c < ell_r)
+//   side 1: P_k[be, j] = sum_al h_k[al, be] Psi2[al, j]     (j < ell_l)
+// stored per instance as [c][k][row] (row fastest): side 0 first, then side 1;
+// and the rows [k0, k0 + kc) of the filter factors Omega1 (s x ell_r) and
+// Psi1 (s x ell_l), stored per instance column by column (Omega1 first),
+// four columns per generator call.
+struct PseqArgs {
+  const void* h;
+  HankelTables t;
+  void* pall;
+  void* filt;
+  int m, n, ell_r, ell_l, kc;
+  uint64_t seed, w2_base;
+};
+
+template <typename T>
+__global__ __launch_bounds__(256) void hankel_pseq_kernel(PseqArgs a) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int mn = a.m * a.n;
+  const int hp = mn + 1;                   // odd block pitch: the blocks of a wave start on distinct banks
+  T* hs = reinterpret_cast<T*>(smem_raw);  // kc blocks
+  T* wy = hs + a.kc * hp;                  // Omega2 [be][c]
+  T* wz = wy + a.n * a.ell_r;              // Psi2 [al][j]
+  const int b = blockIdx.y;
+  const int tid = threadIdx.x;
+  const int64_t s = a.t.s[b];
+  const int K = (int)(2 * s - 1);
+  const int k0 = blockIdx.x * a.kc;
+  if (k0 >= K) return;
+  const int kn = min(a.kc, K - k0);
+  const T* src = reinterpret_cast<const T*>(a.h) + a.t.h_off[b] + (int64_t)k0 * mn;
+  const int tot = kn * mn;
+  for (int e0 = tid; e0 < tot; e0 += 8 * 256) {
+    T v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int e = e0 + u * 256;
+      v[u] = src[e < tot ? e : 0];
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int e = e0 + u * 256;
+      if (e < tot) hs[(e / mn) * hp + e % mn] = v[u];
+    }
+  }
+  const int nqy = (a.ell_r + 3) / 4, nqz = (a.ell_l + 3) / 4;
+  for (int e = tid; e < a.n * nqy + a.m * nqz; e += 256) {
+    const bool zs = e >= a.n * nqy;
+    const int e2 = zs ? e - a.n * nqy : e;
+    const int nq = zs ? nqz : nqy, ell = zs ? a.ell_l : a.ell_r;
+    const int i = e2 / nq, jq = e2 - (e2 / nq) * nq;
+    double gq[4];
+    gauss_quad(a.seed, a.w2_base | (zs ? 3ull : 1ull), (uint64_t)b, i, jq, gq);
+    T* w = zs ? wz : wy;
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (4 * jq + u < ell) w[i * ell + 4 * jq + u] = (T)gq[u];
+  }
+  __syncthreads();
+  T* py = reinterpret_cast<T*>(a.pall) + a.t.p_off[b];
+  T* pz = py + (int64_t)K * a.m * a.ell_r;
+  // dot products of length `len` over strided LDS operands, eight reads of
+  // each operand issued together (clamped indices, masked products)
+  auto dot = [&](const T* x, int sx, const T* w, int sw, int len) {
+    T v = (T)0;
+    for (int i0 = 0; i0 < len; i0 += 8) {
+      T xv[8], wv[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int i = min(i0 + u, len - 1);
+        xv[u] = x[i * sx];
+        wv[u] = w[i * sw];
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v += (i0 + u < len) ? xv[u] * wv[u] : (T)0;
+    }
+    return v;
+  };
+  // one (block, row) position per thread and pass, all columns in turn
+  for (int p = tid; p < kn * a.m; p += 256) {
+    const int kk = p / a.m, al = p - (p / a.m) * a.m;
+    const T* hrow = hs + kk * hp + al;
+    T* dst = py + (int64_t)(k0 + kk) * a.m + al;
+    for (int c = 0; c < a.ell_r; ++c) dst[(int64_t)c * K * a.m] = dot(hrow, a.m, wy + c, a.ell_r, a.n);
+  }
+  for (int p = tid; p < kn * a.n; p += 256) {
+    const int kk = p / a.n, be = p - (p / a.n) * a.n;
+    const T* hcol = hs + kk * hp + a.m * be;
+    T* dst = pz + (int64_t)(k0 + kk) * a.n + be;
+    for (int j = 0; j < a.ell_l; ++j) dst[(int64_t)j * K * a.n] = dot(hcol, 1, wz + j, a.ell_l, a.m);
+  }
+  // filter rows [k0, k0 + kc) of Omega1 and Psi1
+  if (k0 < s) {
+    const int rows = min((int64_t)a.kc, s - k0);
+    T* fo = reinterpret_cast<T*>(a.filt) + a.t.f_off[b];
+    for (int e = tid; e < rows * (nqy + nqz); e += 256) {
+      const int q = e / rows, jr = e - (e / rows) * rows;
+      const bool zs = q >= nqy;
+      const int jq = zs ? q - nqy : q, ell = zs ? a.ell_l : a.ell_r;
+      double gq[4];
+      gauss_quad(a.seed, a.w2_base | (zs ? 2ull : 0ull), (uint64_t)b, k0 + jr, jq, gq);
+      T* col = fo + (zs ? (int64_t)a.ell_r * s : 0);
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if (4 * jq + u < ell) col[(int64_t)(4 * jq + u) * s + k0 + jr] = (T)gq[u];
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Sketch: persistent workgroups over (instance, side, column, row chunk).
 // ---------------------------------------------------------------------------
 struct SketchArgsH {
-  const void* h;
+  const void* pall;
+  const void* filt;
   HankelTables t;
   void* y;
   void* z;
@@ -117,7 +239,6 @@ struct SketchArgsH {
   int rp[2], hs[2], ach[2];
   int items_side0, ipi, total;
   int fl_cap, kp_cap;
-  uint64_t seed, w2_base;
 };
 
 template <typename T>
@@ -143,8 +264,7 @@ __global__ __launch_bounds__(kSkThreads) void hankel_sketch_kernel(SketchArgsH a
   using Acc = typename M::Acc;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* filt = reinterpret_cast<T*>(smem_raw);  // filt[x + 16] = f[x], zero outside [0, s)
-  T* wv = filt + a.fl_cap;                   // the inner factor column (<= 64 entries)
-  T* P = wv + kHankelMaxBlock;               // P[k][rr], kp_cap x rp
+  T* P = filt + a.fl_cap;                    // P[k][rr], kp_cap x rp
   __shared__ int item_sh;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int n16 = lane & 15, g = lane >> 4;
@@ -164,36 +284,63 @@ __global__ __launch_bounds__(kSkThreads) void hankel_sketch_kernel(SketchArgsH a
     const int ac = loc - c * achs;
     const int Rp = a.rp[side], H = a.hs[side];
     const int R = side ? a.n : a.m;  // rows of a block of the output
-    const int I = side ? a.m : a.n;  // contracted block dimension
     const int r0 = ac * Rp;
     const int nr = min(Rp, R - r0);
     const int s = (int)a.t.s[b];
     const int kend = (s + 15 + 3) / 4 * 4;  // a row tile reduces over k < s + 15
     const int ntiles = (s + 16 * H - 1) / (16 * H);
     const int kp_rows = 16 * H * ntiles + kend;
-    const uint64_t fid_filter = side ? 2 : 0, fid_inner = side ? 3 : 1;
-
-    for (int e = tid; e < kend + 16; e += kSkThreads) {
-      const int x = e - 16;
-      filt[e] = (x >= 0 && x < s) ? (T)gauss_entry(a.seed, a.w2_base | fid_filter, (uint64_t)b, x, c) : (T)0;
-    }
-    for (int e = tid; e < I; e += kSkThreads)
-      wv[e] = (T)gauss_entry(a.seed, a.w2_base | fid_inner, (uint64_t)b, e, c);
-    __syncthreads();
-    // P[k][rr] = sum_i h_k[r0 + rr, i] w[i] (side 0), sum_i h_k[i, r0 + rr] w[i] (side 1)
-    const T* hb = reinterpret_cast<const T*>(a.h) + a.t.h_off[b];
-    const int64_t mn = (int64_t)a.m * a.n;
-    const int K = 2 * s - 1;
-    const int64_t stride_i = side ? 1 : a.m;
-    const int64_t stride_r = side ? a.m : 1;
-    for (int e = tid; e < kp_rows * Rp; e += kSkThreads) {
-      const int k = e / Rp, rr = e - (e / Rp) * Rp;
-      T v = (T)0;
-      if (k < K && rr < nr) {
-        const T* hk = hb + (int64_t)k * mn + (int64_t)(r0 + rr) * stride_r;
-        for (int i = 0; i < I; ++i) v += hk[i * stride_i] * wv[i];
+    // the filter column (Omega1 or Psi1), zero outside [0, s)
+    const T* fcol = reinterpret_cast<const T*>(a.filt) + a.t.f_off[b] + (side ? (int64_t)a.ell_r * s : 0) +
+                    (int64_t)c * s;
+    for (int e0 = tid; e0 < kend + 16; e0 += 4 * kSkThreads) {
+      T v[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int x = e0 + u * kSkThreads - 16;
+        const T f = fcol[min(max(x, 0), s - 1)];
+        v[u] = (x >= 0 && x < s) ? f : (T)0;
       }
-      P[e] = v;
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if (e0 + u * kSkThreads < kend + 16) filt[e0 + u * kSkThreads] = v[u];
+    }
+    // the P sequence of this column and block-row chunk (rows k < 2 s - 1,
+    // zero beyond), loaded in batches of independent loads
+    const int K = 2 * s - 1;
+    const T* pa = reinterpret_cast<const T*>(a.pall) + a.t.p_off[b] +
+                  (side ? (int64_t)K * a.m * a.ell_r : 0) + (int64_t)c * K * R + r0;
+    const int tot = kp_rows * Rp;
+    if (Rp == R) {
+      // whole blocks: the slice is contiguous, P[e] = pa[e] for e < K R
+      const int valid = K * R;
+      for (int e0 = tid; e0 < tot; e0 += 16 * kSkThreads) {
+        T v[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+          const int e = e0 + u * kSkThreads;
+          const T x = pa[min(e, valid - 1)];
+          v[u] = e < valid ? x : (T)0;
+        }
+#pragma unroll
+        for (int u = 0; u < 16; ++u)
+          if (e0 + u * kSkThreads < tot) P[e0 + u * kSkThreads] = v[u];
+      }
+    } else {
+      for (int e0 = tid; e0 < tot; e0 += 16 * kSkThreads) {
+        T v[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+          const int e = e0 + u * kSkThreads;
+          const int k = e / Rp, rr = e - (e / Rp) * Rp;
+          const bool ok = e < tot && k < K && rr < nr;
+          const T x = pa[ok ? (int64_t)k * R + rr : 0];
+          v[u] = ok ? x : (T)0;
+        }
+#pragma unroll
+        for (int u = 0; u < 16; ++u)
+          if (e0 + u * kSkThreads < tot) P[e0 + u * kSkThreads] = v[u];
+      }
     }
     __syncthreads();
 
@@ -242,6 +389,7 @@ struct ChunkArgs {
   HankelTables t;
   const void* y;
   const void* z;
+  const void* filt;    // filter columns (Psi1 for the rows of Psi)
   double* part;        // per chunk partial matrices
   const double* rinv;  // per instance R_cum^{-1} (ell_r x ell_r, row-major)
   int m, n, ell_r, ell_l;
@@ -273,14 +421,27 @@ __device__ __forceinline__ void gram_tile(doublex4& acc, const double* X, int ti
 
 // Stages rows [row0, row0 + kSub) of an (nrows x cols) column-major matrix
 // into LDS (row-major, pitch kSP, zero past nrows and for columns in
-// [cols, cpad)).
+// [cols, cpad)).  Every thread issues all its loads before any store; the
+// addresses of the masked entries are clamped to a valid one.
 template <typename T>
 __device__ __forceinline__ void stage_rows(const T* src, int64_t nrows, int cols, int cpad, int64_t row0,
                                            double* dst) {
-  for (int e = threadIdx.x; e < kSub * cpad; e += kChThreads) {
-    const int c = e / kSub, rl = e - (e / kSub) * kSub;
+  constexpr int kIter = kSub * kHankelMaxEll / kChThreads;
+  const int tot = kSub * cpad;
+  double v[kIter];
+#pragma unroll
+  for (int u = 0; u < kIter; ++u) {
+    const int e = threadIdx.x + u * kChThreads;
+    const int c = e / kSub, rl = e % kSub;
     const int64_t row = row0 + rl;
-    dst[rl * kSP + c] = (c < cols && row < nrows) ? (double)src[row + nrows * c] : 0.0;
+    const bool ok = e < tot && c < cols && row < nrows;
+    const T x = src[ok ? row + nrows * c : 0];
+    v[u] = ok ? (double)x : 0.0;
+  }
+#pragma unroll
+  for (int u = 0; u < kIter; ++u) {
+    const int e = threadIdx.x + u * kChThreads;
+    if (e < tot) dst[(e % kSub) * kSP + e / kSub] = v[u];
   }
 }
 
@@ -334,30 +495,29 @@ __global__ __launch_bounds__(kChThreads) void hankel_gram_kernel(ChunkArgs a) {
     __syncthreads();
     stage_rows<T>(Y, ny, lr, 16 * TR, row0, xs);
     if (FIRST) {
-      // Psi rows (a, al): Psi1[a, j] Psi2[al, j]; Psi1 by quads of columns
-      const int nq = (ll + 3) / 4;
-      const int64_t a_lo = row0 / a.m;
-      const int64_t a_hi = min((row0 + kSub - 1) / a.m, s - 1);
-      for (int e = tid; e < (int)(a_hi - a_lo + 1) * nq; e += kChThreads) {
-        const int ar = e / nq, jq = e - (e / nq) * nq;
-        const int64_t aa = a_lo + ar;
-        double gq[4];
-        gauss_quad(a.seed, a.w2_base | 2ull, (uint64_t)b, aa, jq, gq);
-        for (int al = 0; al < a.m; ++al) {
-          const int64_t rl = aa * a.m + al - row0;
-          if (rl < 0 || rl >= kSub || aa * a.m + al >= ny) continue;
+      // Psi rows (a, al): Psi1[a, j] Psi2[al, j], Psi1 from the filter
+      // buffer; a thread's entries share one row (rl = tid % kSub), loads
+      // clamped to valid addresses, zero past ell_l and past the end of Y
+      const int rl = tid % kSub;
+      const int64_t row = row0 + rl;
+      const int64_t rowc = row < ny ? row : ny - 1;
+      const int64_t aa = rowc / a.m;
+      const int al = (int)(rowc - aa * a.m);
+      const T* psi1 = reinterpret_cast<const T*>(a.filt) + a.t.f_off[b] + (int64_t)lr * s;
+      constexpr int kIter = kSub * kHankelMaxEll / kChThreads;
+      const int jw = 16 * TL;
+      double pv[kIter];
 #pragma unroll
-          for (int u = 0; u < 4; ++u) {
-            const int j = 4 * jq + u;
-            if (j < ll) ps[rl * kSP + j] = gq[u] * aux[al * kSP + j];
-          }
-        }
+      for (int u = 0; u < kIter; ++u) {
+        const int j = tid / kSub + u * (kChThreads / kSub);
+        const int jc = j < ll ? j : ll - 1;
+        const double f = (double)psi1[(int64_t)jc * s + aa];
+        pv[u] = (j < ll && row < ny) ? f * aux[al * kSP + jc] : 0.0;
       }
-      // zero: Psi columns past ell_l (up to the tile padding) and rows past
-      // the end of Y (the generation above leaves both untouched)
-      for (int e = tid; e < kSub * 16 * TL; e += kChThreads) {
-        const int rl = e / (16 * TL), j = e - (e / (16 * TL)) * (16 * TL);
-        if (j >= ll || row0 + rl >= ny) ps[rl * kSP + j] = 0.0;
+#pragma unroll
+      for (int u = 0; u < kIter; ++u) {
+        const int j = tid / kSub + u * (kChThreads / kSub);
+        if (j < jw) ps[rl * kSP + j] = pv[u];
       }
     }
     __syncthreads();
@@ -509,7 +669,14 @@ __global__ __launch_bounds__(kElimThreads) void hankel_pass_kernel(SmallArgs a) 
   const int nsum = a.pass == 1 ? lr * lr + ll * lr + ll * ll : lr * lr;
   for (int e = tid; e < nsum; e += kElimThreads) {
     double v = 0.0;
-    for (int c = 0; c < nch; ++c) v += a.part[(ch0 + c) * a.part_stride + e];
+    for (int c0 = 0; c0 < nch; c0 += 8) {
+      double x[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) x[u] = a.part[(ch0 + min(c0 + u, nch - 1)) * a.part_stride + e];
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        if (c0 + u < nch) v += x[u];
+    }
     if (e < lr * lr) {
       const int i = e % lr, j = e / lr;
       sh.g[i * kElimPitch + j] = v;
@@ -741,9 +908,30 @@ struct FinArgs {
   int m, n, ell_r, ell_l, r;
 };
 
+// x . b for a zero-padded row x (registers) and a table column b (LDS, 16-byte
+// aligned): 16 table entries read at a time, four partial sums.  The argmax
+// and the write pass use the same function, so a value is computed the same
+// way in both.
+__device__ __forceinline__ double dot_row(const double (&x)[kHankelMaxEll], const double* b) {
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int k0 = 0; k0 < kHankelMaxEll; k0 += 16) {
+    double bl[16];
+#pragma unroll
+    for (int u = 0; u < 16; u += 2) {
+      const double2 t = *reinterpret_cast<const double2*>(b + k0 + u);
+      bl[u] = t.x;
+      bl[u + 1] = t.y;
+    }
+#pragma unroll
+    for (int u = 0; u < 16; ++u) acc[u & 3] = fma(x[k0 + u], bl[u], acc[u & 3]);
+  }
+  return (acc[0] + acc[1]) + (acc[2] + acc[3]);
+}
+
 template <typename T>
 __global__ __launch_bounds__(kChThreads) void hankel_argmax_kernel(FinArgs a) {
-  __shared__ double bu[kHankelMaxEll * kHankelMaxEll];
+  __shared__ __align__(16) double bu[kHankelMaxEll * kHankelMaxEll];
   __shared__ double rv[kChThreads / 64][kHankelMaxEll];
   __shared__ double ru[kChThreads / 64][kHankelMaxEll];
   __shared__ int64_t ri[kChThreads / 64][kHankelMaxEll];
@@ -754,18 +942,22 @@ __global__ __launch_bounds__(kChThreads) void hankel_argmax_kernel(FinArgs a) {
   const int64_t s = a.t.s[b];
   const int64_t ny = (int64_t)a.m * s;
   const int64_t row = (ch - a.t.ch_off[b]) * kHankelChRows + tid;
-  for (int e = tid; e < lr * r; e += kChThreads) bu[e] = a.bu[(int64_t)b * lr * r + e];
+  // B_U column j at bu[j * kHankelMaxEll + k], zero for k >= ell_r
+  for (int e = tid; e < kHankelMaxEll * r; e += kChThreads) {
+    const int k = e % kHankelMaxEll, j = e / kHankelMaxEll;
+    bu[e] = k < lr ? a.bu[(int64_t)b * lr * r + k + lr * j] : 0.0;
+  }
   __syncthreads();
   const T* Y = reinterpret_cast<const T*>(a.y) + a.t.y_off[b];
   double yv[kHankelMaxEll];
   const bool valid = row < ny;
 #pragma unroll
-  for (int k = 0; k < kHankelMaxEll; ++k) yv[k] = (valid && k < lr) ? (double)Y[row + ny * k] : 0.0;
+  for (int k = 0; k < kHankelMaxEll; ++k) {
+    const T x = Y[(valid ? row : 0) + ny * (k < lr ? k : 0)];
+    yv[k] = (valid && k < lr) ? (double)x : 0.0;
+  }
   for (int j = 0; j < r; ++j) {
-    double u = 0.0;
-#pragma unroll
-    for (int k = 0; k < kHankelMaxEll; ++k)
-      if (k < lr) u += yv[k] * bu[k + lr * j];
+    const double u = dot_row(yv, bu + j * kHankelMaxEll);
     double best = valid ? fabs(u) : -1.0;
     int64_t bi = valid ? row : INT64_MAX;
     double bu_v = u;
@@ -806,8 +998,8 @@ __global__ __launch_bounds__(kChThreads) void hankel_argmax_kernel(FinArgs a) {
 // order), then U = sgn (Y B_U) and V = sgn (Z B_V) for the rows of the chunk.
 template <typename T>
 __global__ __launch_bounds__(kChThreads) void hankel_write_kernel(FinArgs a) {
-  __shared__ double bu[kHankelMaxEll * kHankelMaxEll];
-  __shared__ double bv[kHankelMaxEll * kHankelMaxEll];
+  __shared__ __align__(16) double bu[kHankelMaxEll * kHankelMaxEll];
+  __shared__ __align__(16) double bv[kHankelMaxEll * kHankelMaxEll];
   __shared__ double sgn[kHankelMaxEll];
   const int ch = blockIdx.x;
   const int b = a.t.chunk_inst[ch];
@@ -817,17 +1009,30 @@ __global__ __launch_bounds__(kChThreads) void hankel_write_kernel(FinArgs a) {
   const int64_t ch0 = a.t.ch_off[b];
   const int64_t mx = a.m > a.n ? a.m : a.n;
   const int nch = (int)((mx * s + kHankelChRows - 1) / kHankelChRows);
-  for (int e = tid; e < lr * r; e += kChThreads) bu[e] = a.bu[(int64_t)b * lr * r + e];
-  for (int e = tid; e < ll * r; e += kChThreads) bv[e] = a.bv[(int64_t)b * ll * r + e];
+  // B_U, B_V column j at [j * kHankelMaxEll + k], zero past ell_r / ell_l
+  for (int e = tid; e < kHankelMaxEll * r; e += kChThreads) {
+    const int k = e % kHankelMaxEll, j = e / kHankelMaxEll;
+    bu[e] = k < lr ? a.bu[(int64_t)b * lr * r + k + lr * j] : 0.0;
+    bv[e] = k < ll ? a.bv[(int64_t)b * ll * r + k + ll * j] : 0.0;
+  }
   for (int j = tid; j < r; j += kChThreads) {
     double best = -2.0, bu_v = 0.0, bi = 0.0;
-    for (int c = 0; c < nch; ++c) {
-      const double* p = a.am + ((ch0 + c) * r + j) * 3;
-      if (p[0] > best || (p[0] == best && p[1] < bi)) {
-        best = p[0];
-        bi = p[1];
-        bu_v = p[2];
+    for (int c0 = 0; c0 < nch; c0 += 8) {
+      double pv[8][3];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const double* p = a.am + ((ch0 + min(c0 + u, nch - 1)) * r + j) * 3;
+        pv[u][0] = p[0];
+        pv[u][1] = p[1];
+        pv[u][2] = p[2];
       }
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        if (c0 + u < nch && (pv[u][0] > best || (pv[u][0] == best && pv[u][1] < bi))) {
+          best = pv[u][0];
+          bi = pv[u][1];
+          bu_v = pv[u][2];
+        }
     }
     sgn[j] = bu_v < 0.0 ? -1.0 : 1.0;
   }
@@ -838,13 +1043,12 @@ __global__ __launch_bounds__(kChThreads) void hankel_write_kernel(FinArgs a) {
     const T* Y = reinterpret_cast<const T*>(a.y) + a.t.y_off[b];
     double yv[kHankelMaxEll];
 #pragma unroll
-    for (int k = 0; k < kHankelMaxEll; ++k) yv[k] = k < lr ? (double)Y[row + ny * k] : 0.0;
+    for (int k = 0; k < kHankelMaxEll; ++k) {
+      const T x = Y[row + ny * (k < lr ? k : 0)];
+      yv[k] = k < lr ? (double)x : 0.0;
+    }
     for (int j = 0; j < r; ++j) {
-      double u = 0.0;
-#pragma unroll
-      for (int k = 0; k < kHankelMaxEll; ++k)
-        if (k < lr) u += yv[k] * bu[k + lr * j];
-      u *= sgn[j];
+      const double u = sgn[j] * dot_row(yv, bu + j * kHankelMaxEll);
       const int64_t o = a.t.u_off[b] + row + ny * j;
       if (a.out_double) reinterpret_cast<double*>(a.U)[o] = u;
       else reinterpret_cast<float*>(a.U)[o] = (float)u;
@@ -854,13 +1058,12 @@ __global__ __launch_bounds__(kChThreads) void hankel_write_kernel(FinArgs a) {
     const T* Z = reinterpret_cast<const T*>(a.z) + a.t.z_off[b];
     double zv[kHankelMaxEll];
 #pragma unroll
-    for (int k = 0; k < kHankelMaxEll; ++k) zv[k] = k < ll ? (double)Z[row + nz * k] : 0.0;
+    for (int k = 0; k < kHankelMaxEll; ++k) {
+      const T x = Z[row + nz * (k < ll ? k : 0)];
+      zv[k] = k < ll ? (double)x : 0.0;
+    }
     for (int j = 0; j < r; ++j) {
-      double v = 0.0;
-#pragma unroll
-      for (int k = 0; k < kHankelMaxEll; ++k)
-        if (k < ll) v += zv[k] * bv[k + ll * j];
-      v *= sgn[j];
+      const double v = sgn[j] * dot_row(zv, bv + j * kHankelMaxEll);
       const int64_t o = a.t.v_off[b] + row + nz * j;
       if (a.out_double) reinterpret_cast<double*>(a.V)[o] = v;
       else reinterpret_cast<float*>(a.V)[o] = (float)v;
@@ -869,7 +1072,7 @@ __global__ __launch_bounds__(kChThreads) void hankel_write_kernel(FinArgs a) {
 }
 
 size_t sketch_lds_bytes(int fl_cap, int kp_cap, int rp_max, size_t tsz) {
-  return ((size_t)fl_cap + kHankelMaxBlock + (size_t)kp_cap * rp_max) * tsz;
+  return ((size_t)fl_cap + (size_t)kp_cap * rp_max) * tsz;
 }
 
 size_t gram_lds_bytes() { return (size_t)(2 * kSub * kSP + kHankelMaxBlock * kSP) * sizeof(double); }
@@ -950,6 +1153,9 @@ HankelPlan plan_hankel(int batch, const int64_t* s, int m, int n, int r, int ell
   p.sketch_lds = sketch_lds_bytes(p.fl_cap, kp, rpm, tsz);
   p.items_side0 = ell_r * p.ach[0];
   p.items_per_inst = p.items_side0 + ell_l * p.ach[1];
+  p.pseq_kc = std::max(1, std::min(32, 4096 / (m * n)));
+  p.pseq_chunks = (int)((2 * smax - 1 + p.pseq_kc - 1) / p.pseq_kc);
+  p.pseq_lds = ((size_t)p.pseq_kc * (m * n + 1) + (size_t)n * ell_r + (size_t)m * ell_l) * tsz;
   const int per_cu = (int)std::max<size_t>(1, std::min<size_t>(8, (160 * 1024) / std::max<size_t>(p.sketch_lds, 1)));
   p.sketch_grid = (int)std::min<int64_t>((int64_t)device_cus() * per_cu, (int64_t)p.items_per_inst * batch);
   // workspace layout
@@ -961,7 +1167,11 @@ HankelPlan plan_hankel(int batch, const int64_t* s, int m, int n, int r, int ell
   };
   const int64_t B = batch;
   const int lr = ell_r, ll = ell_l;
-  p.off_tab = take((size_t)B * 7 * 8 + (size_t)B * 4 * 2 + (size_t)nch * 4 + 64);
+  int64_t psum = 0;
+  for (int b = 0; b < batch; ++b) psum += (2 * s[b] - 1) * ((int64_t)m * ell_r + (int64_t)n * ell_l);
+  p.off_tab = take((size_t)B * 9 * 8 + (size_t)B * 4 * 2 + (size_t)nch * 4 + 64);
+  p.off_pall = take((size_t)psum * 8);
+  p.off_filt = take((size_t)ssum * (ell_r + ell_l) * 8);
   p.off_y = take((size_t)m * ssum * lr * 8);
   p.off_z = take((size_t)n * ssum * ll * 8);
   p.off_part = take((size_t)nch * (lr * lr + ll * lr + ll * ll) * 8);
@@ -990,7 +1200,9 @@ HankelTables hankel_tables(const HankelPlan& p, char* ws) {
   t.u_off = base + 4 * B;
   t.v_off = base + 5 * B;
   t.ch_off = base + 6 * B;
-  int32_t* ib = reinterpret_cast<int32_t*>(base + 7 * B);
+  t.p_off = base + 7 * B;
+  t.f_off = base + 8 * B;
+  int32_t* ib = reinterpret_cast<int32_t*>(base + 9 * B);
   t.order = ib;
   t.state = ib + B;
   t.chunk_inst = ib + 2 * B;
@@ -1018,8 +1230,30 @@ static hipError_t launch_typed(const HankelPlan& p, const int64_t* s_host, const
   void* y = ws + p.off_y;
   void* z = ws + p.off_z;
 
+  void* pall = ws + p.off_pall;
+  void* filt = ws + p.off_filt;
+  PseqArgs qa{};
+  qa.h = h;
+  qa.t = t;
+  qa.pall = pall;
+  qa.filt = filt;
+  qa.m = p.m;
+  qa.n = p.n;
+  qa.ell_r = p.ell_r;
+  qa.ell_l = p.ell_l;
+  qa.kc = p.pseq_kc;
+  qa.seed = seed;
+  qa.w2_base = w2;
+  e = hipFuncSetAttribute((const void*)hankel_pseq_kernel<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                          (int)p.pseq_lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(hankel_pseq_kernel<T>, dim3(p.pseq_chunks, p.batch), dim3(256), p.pseq_lds, st, qa);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+
   SketchArgsH ka{};
-  ka.h = h;
+  ka.pall = pall;
+  ka.filt = filt;
   ka.t = t;
   ka.y = y;
   ka.z = z;
@@ -1037,8 +1271,6 @@ static hipError_t launch_typed(const HankelPlan& p, const int64_t* s_host, const
   ka.total = p.items_per_inst * p.batch;
   ka.fl_cap = p.fl_cap;
   ka.kp_cap = p.kp_cap;
-  ka.seed = seed;
-  ka.w2_base = w2;
   e = hipFuncSetAttribute((const void*)hankel_sketch_kernel<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
                           (int)p.sketch_lds);
   if (e != hipSuccess) return e;
@@ -1052,6 +1284,7 @@ static hipError_t launch_typed(const HankelPlan& p, const int64_t* s_host, const
   ca.t = t;
   ca.y = y;
   ca.z = z;
+  ca.filt = filt;
   ca.part = part;
   ca.rinv = reinterpret_cast<double*>(ws + p.off_rinv);
   ca.m = p.m;
