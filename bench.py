@@ -333,11 +333,15 @@ def extra_workloads(stream):
     per = [gpu_ms(lambda m=m: krp.sketch(x, [m], [ell], prec="bf16x3"), 10, stream) for m in range(4)]
     allm = gpu_ms(lambda: krp.sketch(x, [0, 1, 2, 3], [ell] * 4, prec="bf16x3"), 10, stream)
     hos = gpu_ms(lambda: krp.hosvd(x, [r] * 4, p, prec="bf16x3", truncate=True), 10, stream)
+    # RHOSVD-KRP-MEMO: one shared factor set, the outer modes reuse mode 0's product
+    allm_memo = gpu_ms(lambda: krp.sketch(x, [0, 1, 2, 3], [ell] * 4, prec="bf16x3", memo=True), 10, stream)
+    hos_memo = gpu_ms(lambda: krp.hosvd(x, [r] * 4, p, prec="bf16x3", truncate=True, memo=True), 10, stream)
     xb = x.numel() * 4
     out["hosvd_128x4"] = dict(
         sketch_ms_by_mode=per, sketch_gbps_by_mode=[(xb + 128 * ell * 4) / t / 1e6 for t in per],
         all_modes_ms=allm, all_modes_gbps_vs_one_read=(xb + 4 * 128 * ell * 4) / allm / 1e6,
-        hosvd_ms=hos)
+        hosvd_ms=hos, memo_all_modes_ms=allm_memo,
+        memo_all_modes_gbps_vs_one_read=(xb + 4 * 128 * ell * 4) / allm_memo / 1e6, memo_hosvd_ms=hos_memo)
     del x
     # 256-instance block-Hankel batch
     w = WORKLOADS["hankel_256_fp32"]

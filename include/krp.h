@@ -70,7 +70,7 @@ enum {
 /* krp_opts.flags */
 enum {
   KRP_FLAG_NO_GRAPH = 1,   /* launch kernels directly instead of a cached HIP graph */
-  KRP_FLAG_AUTOTUNE = 2    /* time candidate sketch tilings on first use of a shape (dims, mode,
+  KRP_FLAG_AUTOTUNE = 2,   /* time candidate sketch tilings on first use of a shape (dims, mode,
                               ell, precision, storage, alignment) on the call's stream and keep the
                               fastest; results are kept per process and in the JSON file
                               $KRP_TUNE_CACHE (default $HOME/.cache/libkrp/sketch_tiles.json).
@@ -78,6 +78,15 @@ enum {
                               tuning is skipped while the stream is being captured.  The
                               tiling changes only the order of the fp64 reduction of partial
                               sums, i.e. results at the rounding level. */
+  KRP_FLAG_MEMO = 4        /* RHOSVD-KRP-MEMO (Section 5.1, Table 1): one shared factor set for
+                              all modes.  Factor j is drawn once with max(ell) columns under
+                              sketch id 0xFFFF (counter word 2 bits 16..31) and factor id j; the
+                              sketch of mode i uses the first ell_i columns of every other
+                              factor.  For krp_hosvd and krp_sketch; krp_sthosvd returns
+                              KRP_EINVAL (its later sketches are of compressed cores).  The
+                              all-mode pass over X then computes the product of a slab with
+                              the shared mode-2 factor once for mode 1 and every outer mode
+                              (the memoised partial MTTKRP). */
 };
 
 typedef struct krp_opts {

@@ -1,5 +1,6 @@
 // All-mode KRP sketch from one pass over X (Algorithm 7, step 3 for every
-// mode at once; each sketch keeps its own fresh factors).
+// mode at once; each sketch keeps its own fresh factors, or all share one
+// set in the memoised variant of Section 5.1).
 //
 // The tensor is viewed as slabs S_o[i0, i1] (modes 1 and 2 of the paper) over
 // the outer index o = (i2, ..., i_{d-1}).  A workgroup owns a 64-row block of
@@ -16,7 +17,11 @@
 //            (MFMA with the slab as B operand, reduced over i0: the slab goes
 //            through a per-wave LDS staging region to get i0 into the
 //            fragments' reduction slots).
-// W^(m)[o, c] is the product of the outer factors' rows of the step.  Each
+// W^(m)[o, c] is the product of the outer factors' rows of the step.  With
+// one shared factor set (RHOSVD-KRP-MEMO) the slab's product with the mode-2
+// factor is the same for mode 0 and every outer mode, so the outer modes'
+// weighted sums take mode 0's product instead of an MFMA of their own (the
+// memoised partial MTTKRP: half the matrix-core work for four modes).  Each
 // workgroup leaves one partial block per mode (its waves summed in fp64 in
 // wave order); the partials are reduced by the fixed-order reduction of the
 // single-mode sketch.  The factor rows a workgroup needs are drawn into LDS
@@ -48,6 +53,8 @@ struct FusedArgs {
   int ell[kMaxDims];
   uint64_t seed;
   uint32_t draw;
+  int memo;   // one shared factor set (counter field "sketch" = kMemoSketch for every factor)
+  int reuse;  // outer modes take the mode-0 product of the slab (shared factors, ell_0 = max ell)
   // factor-table segments (rows of CP columns in LDS)
   int nseg, tab_rows;
   int seg_off[kFuMaxSeg], seg_rows[kFuMaxSeg];
@@ -151,7 +158,8 @@ __global__ __launch_bounds__(512) void fused_sketch_kernel(FusedArgs a) {
     }
     const int m = a.seg_sketch[s];
     double gq[4];
-    gauss_quad(a.seed, counter_word2(a.draw, (uint32_t)m, (uint32_t)a.seg_factor[s]), 0, (uint64_t)row,
+    gauss_quad(a.seed, counter_word2(a.draw, a.memo ? kMemoSketch : (uint32_t)m, (uint32_t)a.seg_factor[s]), 0,
+               (uint64_t)row,
                (uint64_t)q, gq);
     const bool live = inbox && row < limit;
 #pragma unroll
@@ -271,22 +279,48 @@ __global__ __launch_bounds__(512) void fused_sketch_kernel(FusedArgs a) {
       af[m] = Pol::make(v);
     }
     if (want0) {
-      // the step's weight is applied to the product: acc += W^(0)[o, c] (S Omega^(0)_1)
+      // the step's weight is applied to the product: acc += W^(0)[o, c] (S Omega^(0)_1);
+      // with shared factors the same product also feeds the outer modes'
+      // weighted row sums (the memoised partial MTTKRP)
 #pragma unroll
       for (int t = 0; t < NT; ++t) {
         const typename Pol::Frag bf = FS::get(frg, t, lane);
         const float w = outer_weight(z, 0, -1, 16 * t + n);
+        float ts[NOUT];
+#pragma unroll
+        for (int k = 0; k < NOUT; ++k) ts[k] = 0.f;
 #pragma unroll
         for (int m = 0; m < MT; ++m) {
           typename Pol::Acc u = Pol::zero();
           Pol::mma(u, af[m], bf);
 #pragma unroll
           for (int r = 0; r < 4; ++r) acc0[m][t][r] += w * u[r];
+          if (a.reuse) {
+#pragma unroll
+            for (int k = 0; k < NOUT; ++k)
+#pragma unroll
+              for (int r = 0; r < 4; ++r)
+                ts[k] += u[r] * (float)tab[(a.off_r[k + 2] + 4 * Pol::out_row(g, r) + m) * TP + 16 * t + n];
+          }
+        }
+        if (a.reuse) {
+#pragma unroll
+          for (int k = 0; k < NOUT; ++k) {
+            if (!((a.want >> (k + 2)) & 1)) continue;
+            float tk = ts[k];
+            tk += __shfl_xor(tk, 16, 64);
+            tk += __shfl_xor(tk, 32, 64);
+            if (g == 0) {
+              float* dst = &accl[(a.acc_row0[k] + z.dig[k]) * CP + 16 * t + n];
+              *dst += tk * outer_weight(z, k + 2, k, 16 * t + n);
+            }
+          }
         }
       }
     }
 #pragma unroll
     for (int k = 0; k < NOUT; ++k) {
+      if (a.reuse) break;
       const int ms = k + 2;
       if (!((a.want >> ms) & 1)) continue;
 #pragma unroll
@@ -521,7 +555,9 @@ FusedPlan plan_fused(const SketchProblem* pbs, int nmodes) {
   for (int j = 0; j < nmodes; ++j) {
     const SketchProblem& pb = pbs[j];
     if (pb.prec != p0.prec || pb.seed != p0.seed || pb.draw != p0.draw || pb.d != d) return fp;
-    if (pb.sketch_id != (uint32_t)pb.mode) return fp;
+    const bool memo_pb = pb.sketch_id == kMemoSketch;
+    if (!memo_pb && pb.sketch_id != (uint32_t)pb.mode) return fp;
+    if (memo_pb != (p0.sketch_id == kMemoSketch)) return fp;
     want |= 1 << pb.mode;
     ell[pb.mode] = pb.ell;
     lmax = std::max(lmax, pb.ell);
@@ -627,6 +663,10 @@ FusedPlan plan_fused(const SketchProblem* pbs, int nmodes) {
   for (int m = 0; m < d; ++m) a.ell[m] = ell[m];
   a.seed = p0.seed;
   a.draw = p0.draw;
+  a.memo = p0.sketch_id == kMemoSketch ? 1 : 0;
+  // the outer modes reuse the mode-0 product when every mode is sketched
+  // with the shared factors and mode 0 has the widest column range
+  a.reuse = (a.memo && want == (1 << d) - 1 && ell[0] == lmax) ? 1 : 0;
   fp.args_bytes = sizeof(FusedArgs);
   static_assert(sizeof(FusedArgs) <= sizeof(fp.args), "FusedPlan::args holds FusedArgs");
   std::memcpy(fp.args, &a, sizeof(FusedArgs));

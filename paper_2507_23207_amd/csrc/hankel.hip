@@ -132,14 +132,14 @@ struct PseqArgs {
   uint64_t seed, w2_base;
 };
 
-template <typename T>
+template <typename T, int NB>
 __global__ __launch_bounds__(256) void hankel_pseq_kernel(PseqArgs a) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int mn = a.m * a.n;
   const int hp = mn + 1;                   // odd block pitch: the blocks of a wave start on distinct banks
-  T* hs = reinterpret_cast<T*>(smem_raw);  // kc blocks
-  T* wy = hs + a.kc * hp;                  // Omega2 [be][c]
-  T* wz = wy + a.n * a.ell_r;              // Psi2 [al][j]
+  T* wy = reinterpret_cast<T*>(smem_raw);  // Omega2 by column: wy[c * NB + be], zero for be >= n
+  T* wz = wy + a.ell_r * NB;               // Psi2 by column: wz[j * NB + al], zero for al >= m
+  T* hs = wz + a.ell_l * NB;               // kc blocks
   const int b = blockIdx.y;
   const int tid = threadIdx.x;
   const int64_t s = a.t.s[b];
@@ -162,6 +162,8 @@ __global__ __launch_bounds__(256) void hankel_pseq_kernel(PseqArgs a) {
       if (e < tot) hs[(e / mn) * hp + e % mn] = v[u];
     }
   }
+  for (int e = tid; e < (a.ell_r + a.ell_l) * NB; e += 256) wy[e] = (T)0;
+  __syncthreads();
   const int nqy = (a.ell_r + 3) / 4, nqz = (a.ell_l + 3) / 4;
   for (int e = tid; e < a.n * nqy + a.m * nqz; e += 256) {
     const bool zs = e >= a.n * nqy;
@@ -173,40 +175,48 @@ __global__ __launch_bounds__(256) void hankel_pseq_kernel(PseqArgs a) {
     T* w = zs ? wz : wy;
 #pragma unroll
     for (int u = 0; u < 4; ++u)
-      if (4 * jq + u < ell) w[i * ell + 4 * jq + u] = (T)gq[u];
+      if (4 * jq + u < ell) w[(4 * jq + u) * NB + i] = (T)gq[u];
   }
   __syncthreads();
   T* py = reinterpret_cast<T*>(a.pall) + a.t.p_off[b];
   T* pz = py + (int64_t)K * a.m * a.ell_r;
-  // dot products of length `len` over strided LDS operands, eight reads of
-  // each operand issued together (clamped indices, masked products)
-  auto dot = [&](const T* x, int sx, const T* w, int sw, int len) {
-    T v = (T)0;
-    for (int i0 = 0; i0 < len; i0 += 8) {
-      T xv[8], wv[8];
-#pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        const int i = min(i0 + u, len - 1);
-        xv[u] = x[i * sx];
-        wv[u] = w[i * sw];
-      }
-#pragma unroll
-      for (int u = 0; u < 8; ++u) v += (i0 + u < len) ? xv[u] * wv[u] : (T)0;
-    }
-    return v;
-  };
-  // one (block, row) position per thread and pass, all columns in turn
+  // one (block, row) position per thread and pass: its row (or column) of
+  // the block in registers, then every factor column in turn (broadcast reads)
   for (int p = tid; p < kn * a.m; p += 256) {
     const int kk = p / a.m, al = p - (p / a.m) * a.m;
     const T* hrow = hs + kk * hp + al;
+    T hv[NB];
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+      const T x = hrow[a.m * min(i, a.n - 1)];
+      hv[i] = i < a.n ? x : (T)0;
+    }
     T* dst = py + (int64_t)(k0 + kk) * a.m + al;
-    for (int c = 0; c < a.ell_r; ++c) dst[(int64_t)c * K * a.m] = dot(hrow, a.m, wy + c, a.ell_r, a.n);
+    for (int c = 0; c < a.ell_r; ++c) {
+      const T* w = wy + c * NB;
+      T v = (T)0;
+#pragma unroll
+      for (int i = 0; i < NB; ++i) v += hv[i] * w[i];
+      dst[(int64_t)c * K * a.m] = v;
+    }
   }
   for (int p = tid; p < kn * a.n; p += 256) {
     const int kk = p / a.n, be = p - (p / a.n) * a.n;
     const T* hcol = hs + kk * hp + a.m * be;
+    T hv[NB];
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+      const T x = hcol[min(i, a.m - 1)];
+      hv[i] = i < a.m ? x : (T)0;
+    }
     T* dst = pz + (int64_t)(k0 + kk) * a.n + be;
-    for (int j = 0; j < a.ell_l; ++j) dst[(int64_t)j * K * a.n] = dot(hcol, 1, wz + j, a.ell_l, a.m);
+    for (int j = 0; j < a.ell_l; ++j) {
+      const T* w = wz + j * NB;
+      T v = (T)0;
+#pragma unroll
+      for (int i = 0; i < NB; ++i) v += hv[i] * w[i];
+      dst[(int64_t)j * K * a.n] = v;
+    }
   }
   // filter rows [k0, k0 + kc) of Omega1 and Psi1
   if (k0 < s) {
@@ -1155,7 +1165,7 @@ HankelPlan plan_hankel(int batch, const int64_t* s, int m, int n, int r, int ell
   p.items_per_inst = p.items_side0 + ell_l * p.ach[1];
   p.pseq_kc = std::max(1, std::min(32, 4096 / (m * n)));
   p.pseq_chunks = (int)((2 * smax - 1 + p.pseq_kc - 1) / p.pseq_kc);
-  p.pseq_lds = ((size_t)p.pseq_kc * (m * n + 1) + (size_t)n * ell_r + (size_t)m * ell_l) * tsz;
+  p.pseq_lds = ((size_t)p.pseq_kc * (m * n + 1) + (size_t)kHankelMaxBlock * (ell_r + ell_l)) * tsz;
   const int per_cu = (int)std::max<size_t>(1, std::min<size_t>(8, (160 * 1024) / std::max<size_t>(p.sketch_lds, 1)));
   p.sketch_grid = (int)std::min<int64_t>((int64_t)device_cus() * per_cu, (int64_t)p.items_per_inst * batch);
   // workspace layout
@@ -1244,10 +1254,15 @@ static hipError_t launch_typed(const HankelPlan& p, const int64_t* s_host, const
   qa.kc = p.pseq_kc;
   qa.seed = seed;
   qa.w2_base = w2;
-  e = hipFuncSetAttribute((const void*)hankel_pseq_kernel<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                          (int)p.pseq_lds);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(hankel_pseq_kernel<T>, dim3(p.pseq_chunks, p.batch), dim3(256), p.pseq_lds, st, qa);
+  {
+    const int nb_need = std::max(p.m, p.n);
+    auto pk = nb_need <= 8 ? hankel_pseq_kernel<T, 8>
+              : nb_need <= 16 ? hankel_pseq_kernel<T, 16>
+              : nb_need <= 32 ? hankel_pseq_kernel<T, 32> : hankel_pseq_kernel<T, 64>;
+    e = hipFuncSetAttribute((const void*)pk, hipFuncAttributeMaxDynamicSharedMemorySize, (int)p.pseq_lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(pk, dim3(p.pseq_chunks, p.batch), dim3(256), p.pseq_lds, st, qa);
+  }
   e = hipGetLastError();
   if (e != hipSuccess) return e;
 

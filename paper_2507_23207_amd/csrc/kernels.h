@@ -31,8 +31,11 @@ struct SketchProblem {
   int prec = 0;               // Prec
   uint64_t seed = 0;
   uint32_t draw = 0;
-  uint32_t sketch_id = 0;     // counter field "sketch" (normally == mode)
+  uint32_t sketch_id = 0;     // counter field "sketch" (normally == mode; kMemoSketch: shared set)
 };
+
+// Counter field "sketch" of the shared factor set of RHOSVD-KRP-MEMO.
+constexpr uint32_t kMemoSketch = 0xFFFF;
 
 struct SketchPlan {
   int fmode, n_out;

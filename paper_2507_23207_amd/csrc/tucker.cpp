@@ -72,6 +72,8 @@ int plan_tucker(bool sthosvd, int dtype, int d, const int64_t* dims, const int32
   s.out64 = (o.prec == KRP_P_FP64);
   if (!rank) return set_error(KRP_EINVAL, "rank is NULL");
   if (oversample < 0) return set_error(KRP_EINVAL, "oversample must be >= 0");
+  if (sthosvd && (o.flags & KRP_FLAG_MEMO))
+    return set_error(KRP_EINVAL, "KRP_FLAG_MEMO applies to krp_hosvd and krp_sketch, not to krp_sthosvd");
   for (int k = 0; k < d; ++k) {
     s.dims[k] = dims[k];
     if (rank[k] < 1) return set_error(KRP_EINVAL, "rank[%d]=%d must be >= 1", k, rank[k]);
@@ -113,7 +115,7 @@ int plan_tucker(bool sthosvd, int dtype, int d, const int64_t* dims, const int32
     pb.prec = o.prec;
     pb.seed = o.seed;
     pb.draw = o.draw;
-    pb.sketch_id = (uint32_t)m;
+    pb.sketch_id = (o.flags & KRP_FLAG_MEMO) ? kMemoSketch : (uint32_t)m;
     s.spl[step] = plan_sketch(pb, tile);
     part_max = std::max(part_max, s.spl[step].partial_bytes);
     part_max = std::max(part_max, cholqr_split_bytes(pb.dims[m], s.ell[m]));  // reused by the QR
@@ -194,7 +196,7 @@ std::string tucker_key(const TuckerSetup& s, const krp_opts& o, const void* X, c
     k += "|" + std::to_string(s.dims[i]) + "," + std::to_string(s.rank[i]) + "," +
          std::to_string(s.ell[i]) + "," + std::to_string(s.order[i]) + "," + ptr_key(Q[i]);
   k += "|seed=" + std::to_string(o.seed) + "|draw=" + std::to_string(o.draw) +
-       "|tr=" + std::to_string(o.truncate) + "|err=" + std::to_string(want_err ? 1 : 0) +
+       "|memo=" + std::to_string((o.flags & KRP_FLAG_MEMO) ? 1 : 0) + "|tr=" + std::to_string(o.truncate) + "|err=" + std::to_string(want_err ? 1 : 0) +
        "|X=" + ptr_key(X) + "|core=" + ptr_key(core) + "|ws=" + ptr_key(ws) + "|" +
        "|st=" + ptr_key(status);
   for (int i = 0; i < s.n_sketch; ++i) k += "|t=" + plan_key(s.spl[i]);  // tilings (tuned or not)
@@ -448,7 +450,7 @@ int prepare_sketches(const void* X, int dtype, int d, const int64_t* dims, int n
     pb.prec = o.prec;
     pb.seed = o.seed;
     pb.draw = o.draw;
-    pb.sketch_id = (uint32_t)m;
+    pb.sketch_id = (o.flags & KRP_FLAG_MEMO) ? kMemoSketch : (uint32_t)m;
     ss.pl[j] = plan_sketch(pb, SketchTile{});
     if (tune) {
       const SketchPlan t = plan_sketch(pb, tuned_tile(pb, st));
@@ -503,6 +505,7 @@ int krp_sketch(const void* X, int dtype, int d, const int64_t* dims, int nmodes,
     key += "|" + std::to_string(modes[j]) + "," + std::to_string(ell[j]) + "," + ptr_key(Y[j]) + ",t=" +
            plan_key(ss.pl[j]);
   key += ss.fused ? "|fused" : "";
+  key += (o.flags & KRP_FLAG_MEMO) ? "|memo" : "";
   return run_maybe_graph(key, !(o.flags & KRP_FLAG_NO_GRAPH), st,
                          [&](hipStream_t cs) -> int { return enqueue_sketches(ss, ws, Y, cs); });
 }

@@ -74,10 +74,11 @@ def test_sketch_rejects_before_gpu(L, kw):
 
 
 def _tucker(L, fn="krp_hosvd", dims=(8, 8, 8), rank=(2, 2, 2), p=2, order=None, truncate=0, q_null=False,
-            core=FAKE):
+            core=FAKE, flags=0):
     o = _capi.KrpOpts()
     L.krp_opts_default(ctypes.byref(o))
     o.truncate = truncate
+    o.flags = flags
     keep = None
     if order is not None:
         keep = _capi.i32_array(order)
@@ -99,6 +100,14 @@ def _tucker(L, fn="krp_hosvd", dims=(8, 8, 8), rank=(2, 2, 2), p=2, order=None, 
 ])
 def test_tucker_rejects_before_gpu(L, fn, kw):
     assert _tucker(L, fn=fn, **kw) == _capi.KRP_EINVAL
+
+
+def test_memo_flag_is_for_hosvd_only(L):
+    """RHOSVD-KRP-MEMO shares one factor set over the modes of one tensor; the
+    STHOSVD sketches are of successively compressed cores, so the flag is
+    rejected there (before any GPU call)."""
+    assert _tucker(L, fn="krp_sthosvd", flags=_capi.KRP_FLAG_MEMO) == _capi.KRP_EINVAL
+    assert "MEMO" in L.krp_last_error().decode()
 
 
 def test_order_validation(L):
