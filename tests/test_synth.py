@@ -29,5 +29,35 @@ def test_hankel_series_shapes():
 
 def test_workloads_consistent():
     for name, w in WORKLOADS.items():
-        if "dims" in w:
+        if "rank" in w:
             assert all(w["rank"] + w["p"] <= n for n in w["dims"])
+        if "ranks" in w:  # rank sweeps (Cauchy, sensor grids)
+            assert all(max(w["ranks"]) + w.get("p", 0) <= min(n, 64) for n in w["dims"])
+
+
+def test_cauchy_tensor_closed_form():
+    import synth
+    x = synth.cauchy_tensor((4, 3, 5, 2), alpha=2.0)
+    assert x.flags.f_contiguous
+    for idx in [(0, 0, 0, 0), (3, 2, 4, 1), (1, 2, 0, 1)]:
+        want = 1.0 / np.sqrt(sum((i + 1) ** 2 for i in idx))
+        assert abs(x[idx] - want) <= 1e-15
+    y = synth.cauchy_tensor((3, 3), alpha=1.0)
+    assert abs(y[2, 1] - 1.0 / 5.0) <= 1e-15
+
+
+def test_flow_snapshots_rank_and_sets():
+    import synth
+    dims = (12, 10, 9)
+    x = synth.flow_snapshots(dims, 20, n_modes=5, noise=0.0, mode_seed=4)
+    assert x.shape == dims + (20,) and x.flags.f_contiguous
+    for m in range(3):  # every spatial unfolding has rank <= the number of modes
+        u = np.moveaxis(x, m, 0).reshape(dims[m], -1)
+        s = np.linalg.svd(u, compute_uv=False)
+        assert s[5:].max(initial=0.0) <= 1e-12 * s[0]
+    t = synth.flow_snapshots(dims, 4, n_modes=5, noise=0.0, mode_seed=4, test_seed=9)
+    # test fields lie in the span of the training modes
+    u = np.moveaxis(x, 0, 0).reshape(dims[0], -1)
+    q = np.linalg.svd(u, full_matrices=False)[0][:, :5]
+    ut = t.reshape(dims[0], -1, order="F")
+    assert np.linalg.norm(ut - q @ (q.T @ ut)) <= 1e-10 * np.linalg.norm(ut)
