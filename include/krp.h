@@ -10,6 +10,11 @@
  *   krp_hankel_lowrank  single-pass randomized SVD of block-Hankel matrices
  *                       with KRPs (Algorithm 6 with the Hankel structure of
  *                       Section 4.2), batched over instances of uneven size.
+ *   krp_range_factors   the orthonormal factors of Algorithm 7 (sketch and
+ *                       CholeskyQR) for some modes, without the core.
+ *   krp_sensor_select, krp_sensor_measure, krp_sensor_reconstruct
+ *                       sensor placement and field reconstruction from the
+ *                       factors (Section 6).
  *
  * Conventions
  *   - Pointers named "device" point to GPU memory of the current HIP device;
@@ -48,7 +53,8 @@ enum {
   KRP_EHIP = 3,        /* a HIP runtime call failed */
   KRP_ECHOL = 4,       /* CholeskyQR broke down even after the shifted fallback */
   KRP_ENONFINITE = 5,  /* a non-finite value reached an orthonormalisation */
-  KRP_ENODEV = 6       /* no usable gfx950 device */
+  KRP_ENODEV = 6,      /* no usable gfx950 device */
+  KRP_ESINGULAR = 7    /* a sensor matrix P_i^T Q_i is singular (krp_sensor_select) */
 };
 
 /* Storage type of tensors, Hankel data and outputs. */
@@ -64,7 +70,8 @@ enum { KRP_P_FP64 = 0, KRP_P_FP32 = 1, KRP_P_BF16 = 2, KRP_P_BF16X3 = 3 };
 enum {
   KRP_STAT_CHOL_SHIFT = 1,  /* shifted CholeskyQR fallback taken (result still valid) */
   KRP_STAT_CHOL_FAIL = 2,   /* breakdown after the fallback (maps to KRP_ECHOL) */
-  KRP_STAT_NONFINITE = 4    /* non-finite input to a QR (maps to KRP_ENONFINITE) */
+  KRP_STAT_NONFINITE = 4,   /* non-finite input to a QR (maps to KRP_ENONFINITE) */
+  KRP_STAT_SINGULAR = 8     /* singular sensor matrix (maps to KRP_ESINGULAR) */
 };
 
 /* krp_opts.flags */
@@ -185,6 +192,70 @@ int krp_sthosvd(const void* X, int dtype, int d, const int64_t* dims, const int3
 int krp_hankel_lowrank(int batch, const int64_t* s, int m, int n, const void* h, int dtype, int r,
                        int ell_r, int ell_l, const krp_opts* opts, void* U, void* S, void* V,
                        void* stream);
+
+/* Orthonormal factors of Algorithm 7 for the listed modes only (steps 2-4:
+ * KRP sketch of each mode unfolding, then CholeskyQR2 with the shifted
+ * fallback), e.g. the spatial factors of Section 6's training phase, where
+ * the snapshot mode is not compressed.  Same factors as krp_sketch /
+ * krp_hosvd draw for those modes (KRP_FLAG_MEMO: the shared set); several
+ * modes of fp32 data take the one-pass fused sketch.
+ *   modes, ell  host, nmodes distinct modes; 1 <= ell[j] <= min(dims[modes[j]], 64)
+ *   Q      host array of nmodes device pointers; Q[j] receives the
+ *          dims[modes[j]] x ell[j] orthonormal factor (column-major, `dtype`)
+ * Status as for krp_hosvd. */
+int krp_range_factors(const void* X, int dtype, int d, const int64_t* dims, int nmodes,
+                      const int32_t* modes, const int32_t* ell, const krp_opts* opts, void* const* Q,
+                      void* stream);
+
+/* Sensor placement, training phase (Section 6): for each of nmodes factors
+ * Q_j (n[j] x ell[j], orthonormal columns, column-major, `dtype`, device),
+ * the column-pivoted QR of Q_j^T chooses the ell[j] sensor indices (greedy
+ * pivoting: the row of Q_j whose part orthogonal to the rows already chosen
+ * is largest, lowest index on ties; fp64 arithmetic) and
+ *   A_j = Q_j (P_j^T Q_j)^{-1}   (n[j] x ell[j], column-major, `dtype`),
+ * P_j^T Q_j being the chosen rows of Q_j, inverted by Gauss-Jordan elimination
+ * with partial pivoting in fp64.  A_j interpolates: its rows at the sensors
+ * form the identity.
+ *   n, ell   host; 1 <= ell[j] <= min(n[j], 64); 1 <= nmodes <= 8
+ *   idx      host array of device int32 pointers; idx[j] receives the ell[j]
+ *            sensor indices (0-based) in pivot order
+ * Returns KRP_ESINGULAR when some Q_j has rank < ell[j] (a pivot's residual
+ * norm at most 64 unit roundoffs of the largest row norm of Q_j; its idx[j] is
+ * then all -1 and A_j zero) and KRP_ENONFINITE for non-finite Q_j; other modes are
+ * unaffected. */
+int krp_sensor_select(int nmodes, const int64_t* n, const int32_t* ell, int dtype, const void* const* Q,
+                      const krp_opts* opts, int32_t* const* idx, void* const* A, void* stream);
+
+/* Sensor placement, test phase: the values of `snapshots` fields on the
+ * sensor grid, T_hat = T(I_1, ..., I_d) (Section 6).
+ *   T      device, dims[0] x ... x dims[d-1] x snapshots (Kolda order, the
+ *          snapshot index slowest), `dtype`; 1 <= d <= 7
+ *   idx    host array of d device int32 pointers, idx[i] with ell[i] entries
+ *   T_hat  device, ell[0] x ... x ell[d-1] x snapshots
+ * An index outside 0..dims[i]-1 yields NaN in the entries that use it (T is
+ * never read outside its extent).  No workspace, no synchronisation. */
+int krp_sensor_measure(const void* T, int dtype, int d, const int64_t* dims, int64_t snapshots,
+                       const int32_t* ell, const int32_t* const* idx, void* T_hat, void* stream);
+
+/* Reconstruction of the fields from their sensor values (Section 6):
+ *   T_out = T_hat x_1 A_1 x_2 ... x_d A_d   (snapshot mode untouched),
+ * on the TTM kernels in natural mode order (the expanding products run in
+ * 64-column chunks of each mode).
+ *   T_hat  device, ell[0] x ... x ell[d-1] x snapshots, `dtype`
+ *   A      host array of d device pointers, A[i] dims[i] x ell[i] column-major
+ *   T_out  device, dims[0] x ... x dims[d-1] x snapshots
+ *   opts->prec  KRP_P_FP64 for fp64 data; fp32 data: KRP_P_FP32, KRP_P_BF16
+ *          or KRP_P_BF16X3 (the factors are taken in fp64 and cast to the
+ *          arithmetic type) */
+int krp_sensor_reconstruct(const void* T_hat, int dtype, int d, const int64_t* dims, int64_t snapshots,
+                           const int32_t* ell, const void* const* A, const krp_opts* opts, void* T_out,
+                           void* stream);
+
+/* Workspace of the sensor calls when the caller provides opts->workspace:
+ * which 0 krp_sensor_select (d modes, dims = n, snapshots ignored), 1
+ * krp_sensor_reconstruct. */
+int krp_sensor_workspace_size(int which, int d, const int64_t* dims, const int32_t* ell, int64_t snapshots,
+                              int dtype, size_t* bytes);
 
 /* Device workspace a call with the same arguments needs when the caller
  * provides opts->workspace.  `which`: 0 sketch (rank[] = ell[] per listed

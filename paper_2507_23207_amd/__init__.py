@@ -21,7 +21,9 @@ PREC = {"fp64": _capi.KRP_P_FP64, "fp32": _capi.KRP_P_FP32, "bf16": _capi.KRP_P_
         "bf16x3": _capi.KRP_P_BF16X3}
 
 __all__ = ["sketch", "sketch_noalloc", "hosvd", "sthosvd", "hankel_lowrank", "gaussian", "kolda", "empty_kolda",
-           "workspace_size", "hankel_workspace_size", "finalize", "version", "KrpError", "PREC"]
+           "range_factors", "sensor_select", "sensor_measure", "sensor_reconstruct",
+           "workspace_size", "hankel_workspace_size", "sensor_workspace_size", "finalize", "version", "KrpError",
+           "PREC"]
 
 
 def _torch():
@@ -177,6 +179,115 @@ def sthosvd(x, ranks, oversample, prec="fp32", seed=2507, draw=0, truncate=False
     """Randomized STHOSVD with KRPs (Algorithm 8); krp_sthosvd.  Returns (core, [Q_i], rel_err)."""
     return _tucker(_capi.lib().krp_sthosvd, x, ranks, oversample, prec, seed, draw, truncate, rel_err,
                    graph, order, workspace, status, autotune)
+
+
+def range_factors(x, modes, ell, prec="fp32", seed=2507, draw=0, graph=True, memo=False, status=None):
+    """Orthonormal factors of Algorithm 7 for the listed modes only (sketch +
+    CholeskyQR2); krp_range_factors.  Returns [Q_j] (column-major)."""
+    torch = _torch()
+    _check_tensor(x)
+    modes = [int(m) for m in modes]
+    ell = [int(v) for v in ell] if hasattr(ell, "__len__") else [int(ell)] * len(modes)
+    qs = [torch.empty((l, x.shape[m]), dtype=x.dtype, device=x.device).t() for m, l in zip(modes, ell)]
+    o, _, keep = _opts(prec, seed, draw, graph=graph, memo=memo, status=status)
+    rc = _capi.lib().krp_range_factors(ctypes.c_void_p(x.data_ptr()), _dtype_code(x), x.dim(),
+                                       _capi.i64_array(x.shape), len(modes), _capi.i32_array(modes),
+                                       _capi.i32_array(ell), ctypes.byref(o),
+                                       _capi.ptr_array([q.data_ptr() for q in qs]), _stream(x))
+    _capi.check(rc)
+    return qs
+
+
+def _check_colmajor(a, rows, cols, dtype, name):
+    if (not a.is_cuda or a.dtype != dtype or tuple(a.shape) != (rows, cols) or a.stride(0) != 1
+            or (cols > 1 and a.stride(1) != rows)):
+        raise ValueError(f"{name} must be a column-major ({rows}, {cols}) GPU tensor of dtype {dtype}")
+
+
+def sensor_select(qs, graph=True, status=None):
+    """Sensor indices and interpolation factors (Section 6); krp_sensor_select.
+
+    ``qs``: column-major (N_j, ell_j) factors with orthonormal columns.
+    Returns ([idx_j] int32 device tensors in pivot order, [A_j])."""
+    torch = _torch()
+    if not qs:
+        raise ValueError("need at least one factor")
+    dt = qs[0].dtype
+    for j, q in enumerate(qs):
+        _check_colmajor(q, q.shape[0], q.shape[1], dt, f"Q[{j}]")
+    n = [int(q.shape[0]) for q in qs]
+    ell = [int(q.shape[1]) for q in qs]
+    dev = qs[0].device
+    idx = [torch.empty(l, dtype=torch.int32, device=dev) for l in ell]
+    a = [torch.empty((l, m), dtype=dt, device=dev).t() for m, l in zip(n, ell)]
+    o, _, keep = _opts("fp64" if dt == torch.float64 else "fp32", 0, 0, graph=graph, status=status)
+    rc = _capi.lib().krp_sensor_select(len(qs), _capi.i64_array(n), _capi.i32_array(ell), _dtype_code(qs[0]),
+                                       _capi.ptr_array([q.data_ptr() for q in qs]), ctypes.byref(o),
+                                       _capi.ptr_array([v.data_ptr() for v in idx]),
+                                       _capi.ptr_array([v.data_ptr() for v in a]), _stream(qs[0]))
+    _capi.check(rc)
+    return idx, a
+
+
+def sensor_measure(t, idx):
+    """T_hat = T(I_1, ..., I_d) for fields ``t`` of shape (N_1..N_d, snapshots)
+    (Kolda strides); krp_sensor_measure.  ``idx``: int32 device tensors."""
+    _check_tensor(t)
+    d = len(idx)
+    if t.dim() != d + 1:
+        raise ValueError("t must have the d spatial modes and a snapshot mode")
+    ell = [int(v.numel()) for v in idx]
+    for v in idx:
+        if not v.is_cuda or v.dtype != _torch().int32 or not v.is_contiguous():
+            raise ValueError("idx entries must be contiguous int32 GPU tensors")
+    out = empty_kolda(ell + [t.shape[d]], t.dtype, t.device)
+    rc = _capi.lib().krp_sensor_measure(ctypes.c_void_p(t.data_ptr()), _dtype_code(t), d,
+                                        _capi.i64_array(t.shape[:d]), int(t.shape[d]), _capi.i32_array(ell),
+                                        _capi.ptr_array([v.data_ptr() for v in idx]),
+                                        ctypes.c_void_p(out.data_ptr()), _stream(t))
+    _capi.check(rc)
+    return out
+
+
+def sensor_reconstruct(t_hat, a, prec=None, graph=True, out=None):
+    """T_hat x_1 A_1 ... x_d A_d (snapshot mode last, untouched);
+    krp_sensor_reconstruct.  ``prec`` defaults to the storage precision."""
+    torch = _torch()
+    _check_tensor(t_hat)
+    d = len(a)
+    if t_hat.dim() != d + 1:
+        raise ValueError("t_hat must have the d sensor modes and a snapshot mode")
+    dims = [int(m.shape[0]) for m in a]
+    ell = [int(m.shape[1]) for m in a]
+    for j, m in enumerate(a):
+        _check_colmajor(m, dims[j], ell[j], t_hat.dtype, f"A[{j}]")
+        if ell[j] != t_hat.shape[j]:
+            raise ValueError(f"A[{j}] has {ell[j]} columns, t_hat mode {j} has {t_hat.shape[j]} entries")
+    if prec is None:
+        prec = "fp64" if t_hat.dtype == torch.float64 else "fp32"
+    snaps = int(t_hat.shape[d])
+    if out is None:
+        out = empty_kolda(dims + [snaps], t_hat.dtype, t_hat.device)
+    elif tuple(out.shape) != tuple(dims + [snaps]) or out.dtype != t_hat.dtype:
+        raise ValueError("out has the wrong shape or dtype")
+    else:
+        _check_tensor(out)
+    o, _, keep = _opts(prec, 0, 0, graph=graph)
+    rc = _capi.lib().krp_sensor_reconstruct(ctypes.c_void_p(t_hat.data_ptr()), _dtype_code(t_hat), d,
+                                            _capi.i64_array(dims), snaps, _capi.i32_array(ell),
+                                            _capi.ptr_array([m.data_ptr() for m in a]), ctypes.byref(o),
+                                            ctypes.c_void_p(out.data_ptr()), _stream(t_hat))
+    _capi.check(rc)
+    return out
+
+
+def sensor_workspace_size(which, dims, ell, snapshots=1, dtype=_capi.KRP_F32):
+    nb = ctypes.c_size_t(0)
+    rc = _capi.lib().krp_sensor_workspace_size(int(which), len(dims), _capi.i64_array(dims),
+                                               _capi.i32_array(ell), int(snapshots), int(dtype),
+                                               ctypes.byref(nb))
+    _capi.check(rc)
+    return nb.value
 
 
 def hankel_lowrank(s, h, m, n, r, ell_r, ell_l=0, prec="fp32", seed=2507, draw=0, graph=True,

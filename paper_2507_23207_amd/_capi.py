@@ -11,10 +11,10 @@ import os
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libkrp.so")
 
-KRP_OK, KRP_EINVAL, KRP_ENOMEM, KRP_EHIP, KRP_ECHOL, KRP_ENONFINITE, KRP_ENODEV = range(7)
+KRP_OK, KRP_EINVAL, KRP_ENOMEM, KRP_EHIP, KRP_ECHOL, KRP_ENONFINITE, KRP_ENODEV, KRP_ESINGULAR = range(8)
 KRP_F64, KRP_F32 = 0, 1
 KRP_P_FP64, KRP_P_FP32, KRP_P_BF16, KRP_P_BF16X3 = 0, 1, 2, 3
-KRP_STAT_CHOL_SHIFT, KRP_STAT_CHOL_FAIL, KRP_STAT_NONFINITE = 1, 2, 4
+KRP_STAT_CHOL_SHIFT, KRP_STAT_CHOL_FAIL, KRP_STAT_NONFINITE, KRP_STAT_SINGULAR = 1, 2, 4, 8
 KRP_FLAG_NO_GRAPH, KRP_FLAG_AUTOTUNE, KRP_FLAG_MEMO = 1, 2, 4
 
 # Every function declared in include/krp.h.
@@ -22,6 +22,8 @@ EXPORTED = (
     "krp_opts_default", "krp_sketch", "krp_hosvd", "krp_sthosvd", "krp_hankel_lowrank",
     "krp_workspace_size", "krp_hankel_workspace_size", "krp_gaussian", "krp_status_string",
     "krp_last_error", "krp_version", "krp_finalize", "krp_sketch_noalloc", "krp_noalloc_scratch_bytes",
+    "krp_range_factors", "krp_sensor_select", "krp_sensor_measure", "krp_sensor_reconstruct",
+    "krp_sensor_workspace_size",
 )
 
 
@@ -74,6 +76,18 @@ def lib() -> ctypes.CDLL:
             f = getattr(L, name)
             f.argtypes = [P, i, i, I64P, I32P, i32, OP, P, ctypes.POINTER(P), I64P, P]
             f.restype = i
+        L.krp_range_factors.argtypes = [P, i, i, I64P, i, I32P, I32P, OP, ctypes.POINTER(P), P]
+        L.krp_range_factors.restype = i
+        L.krp_sensor_select.argtypes = [i, I64P, I32P, i, ctypes.POINTER(P), OP, ctypes.POINTER(P),
+                                        ctypes.POINTER(P), P]
+        L.krp_sensor_select.restype = i
+        L.krp_sensor_measure.argtypes = [P, i, i, I64P, ctypes.c_int64, I32P, ctypes.POINTER(P), P, P]
+        L.krp_sensor_measure.restype = i
+        L.krp_sensor_reconstruct.argtypes = [P, i, i, I64P, ctypes.c_int64, I32P, ctypes.POINTER(P), OP, P, P]
+        L.krp_sensor_reconstruct.restype = i
+        L.krp_sensor_workspace_size.argtypes = [i, i, I64P, I32P, ctypes.c_int64, i,
+                                                ctypes.POINTER(ctypes.c_size_t)]
+        L.krp_sensor_workspace_size.restype = i
         L.krp_hankel_lowrank.argtypes = [i, I64P, i, i, P, i, i, i, i, OP, P, P, P, P]
         L.krp_hankel_lowrank.restype = i
         L.krp_workspace_size.argtypes = [i, i, i, I64P, I32P, i32, i, ctypes.POINTER(ctypes.c_size_t)]

@@ -202,6 +202,7 @@ int finish_status(const int* status_ws, hipStream_t st) {
   e = hipStreamSynchronize(st);
   if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
   if (h & KRP_STAT_NONFINITE) return set_error(KRP_ENONFINITE, "non-finite values reached a QR");
+  if (h & KRP_STAT_SINGULAR) return set_error(KRP_ESINGULAR, "a sensor matrix P^T Q is singular");
   if (h & KRP_STAT_CHOL_FAIL)
     return set_error(KRP_ECHOL, "CholeskyQR broke down after the shifted fallback");
   return KRP_OK;
@@ -235,6 +236,7 @@ const char* krp_status_string(int s) {
     case KRP_ECHOL: return "KRP_ECHOL: CholeskyQR breakdown after the fallback";
     case KRP_ENONFINITE: return "KRP_ENONFINITE: non-finite values";
     case KRP_ENODEV: return "KRP_ENODEV: no usable device";
+    case KRP_ESINGULAR: return "KRP_ESINGULAR: singular sensor matrix";
     default: return "unknown krp status";
   }
 }

@@ -19,6 +19,7 @@ enum StatusBits : int {
   kStatCholShift = 1,    // shifted CholeskyQR fallback was taken
   kStatCholFail = 2,     // Cholesky broke down even with the shift
   kStatNonFinite = 4,    // a non-finite value reached an orthonormalisation
+  kStatSingular = 8,     // a sensor matrix P^T Q is singular (rank-deficient Q)
 };
 
 __device__ __forceinline__ void raise_status(int* status, int bits) {

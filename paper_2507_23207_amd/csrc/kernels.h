@@ -125,7 +125,10 @@ hipError_t launch_cholqr_split(int64_t n, int ell, const double* y64, double* q6
                                int out_is_double, void* ws, int* status, hipStream_t st);
 
 // TTM G_new = G x_mode Q^T for a tensor in Kolda order with current sizes
-// dims (dims[mode] = n rows of Q), Q (n x ell, fp64 column-major).
+// dims (dims[mode] = n rows of Q), Q (n x ell, fp64 column-major).  With
+// out_ld > ell the output mode has extent out_ld and these ell columns are a
+// chunk of it: `out` then points at the chunk's first column (element offset
+// c0 for mode 0, c0 * prod(dims before mode) otherwise).
 struct TtmProblem {
   const void* g = nullptr;
   int g_is_double = 0;
@@ -137,6 +140,7 @@ struct TtmProblem {
   int ell = 0;
   int prec = 0;
   const double* q64 = nullptr;
+  int64_t out_ld = 0;  // 0: ell
 };
 hipError_t launch_ttm(const TtmProblem& pb, hipStream_t st);
 

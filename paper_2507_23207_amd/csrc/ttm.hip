@@ -30,6 +30,7 @@ struct TtmArgs {
   const double* q;
   int64_t P, n, Q;  // g[p, a, q] sizes
   int ell;
+  int64_t ldc;      // extent of the output mode (ell, or more for a column chunk)
   int64_t items;
   int p_groups;     // non-mode-0: p groups per q
 };
@@ -188,11 +189,11 @@ __global__ __launch_bounds__(64 * kTtmWaves) void ttm_kernel(TtmArgs a) {
         if constexpr (MODE0) {
           const int64_t qi = q0 + 16 * m + Pol::out_row(g, r);
           const int c = 16 * t + n;
-          if (qi < a.Q && c < a.ell) out[c + (int64_t)a.ell * qi] = (Tout)acc[m][t][r];
+          if (qi < a.Q && c < a.ell) out[c + a.ldc * qi] = (Tout)acc[m][t][r];
         } else {
           const int c = 16 * m + Pol::out_row(g, r);
           const int64_t pi = p0 + 16 * t + n;
-          if (pi < a.P && c < a.ell) out[pi + a.P * (c + (int64_t)a.ell * qq)] = (Tout)acc[m][t][r];
+          if (pi < a.P && c < a.ell) out[pi + a.P * (c + a.ldc * qq)] = (Tout)acc[m][t][r];
         }
       }
 }
@@ -304,7 +305,7 @@ __global__ __launch_bounds__(64 * kTtmWaves) void ttm_split_kernel(TtmArgs a) {
     const int t = mt % NT, m = mt / NT;
     const int c = 16 * m + Pol::out_row(ln >> 4, r);
     const int64_t pi = p0 + 16 * t + (ln & 15);
-    if (pi < a.P && c < a.ell) out[pi + a.P * (c + (int64_t)a.ell * qq)] = (Tout)sum;
+    if (pi < a.P && c < a.ell) out[pi + a.P * (c + a.ldc * qq)] = (Tout)sum;
   }
 }
 
@@ -397,6 +398,7 @@ hipError_t ttm_dispatch(bool mode0, bool kvec, int tiles_c, const TtmArgs& a, hi
 
 hipError_t launch_ttm(const TtmProblem& pb, hipStream_t st) {
   if (pb.ell < 1 || pb.ell > 64) return hipErrorInvalidValue;
+  if (pb.out_ld != 0 && pb.out_ld < pb.ell) return hipErrorInvalidValue;
   TtmArgs a{};
   a.g = pb.g;
   a.out = pb.out;
@@ -408,6 +410,7 @@ hipError_t launch_ttm(const TtmProblem& pb, hipStream_t st) {
   a.n = pb.dims[pb.mode];
   a.Q = Q;
   a.ell = pb.ell;
+  a.ldc = pb.out_ld > 0 ? pb.out_ld : pb.ell;
   const int tiles_c = (pb.ell + 15) / 16;
   const bool mode0 = (P == 1);
   const int vec = pb.g_is_double ? 2 : 4;

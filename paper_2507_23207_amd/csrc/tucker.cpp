@@ -510,6 +510,67 @@ int krp_sketch(const void* X, int dtype, int d, const int64_t* dims, int nmodes,
                          [&](hipStream_t cs) -> int { return enqueue_sketches(ss, ws, Y, cs); });
 }
 
+int krp_range_factors(const void* X, int dtype, int d, const int64_t* dims, int nmodes, const int32_t* modes,
+                      const int32_t* ell, const krp_opts* opts, void* const* Q, void* stream) {
+  krp_opts o;
+  if (opts)
+    o = *opts;
+  else
+    krp_opts_default(&o);
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  SketchSet ss;
+  // Q stands in for the sketch outputs in the validation; the sketches go to
+  // fp64 workspace buffers
+  KRP_TRY(prepare_sketches(X, dtype, d, dims, nmodes, modes, ell, Q, o, false, st, &ss));
+  for (int j = 0; j < nmodes; ++j)
+    if (ell[j] > dims[modes[j]])
+      return set_error(KRP_EINVAL, "ell[%d]=%d exceeds the mode size %lld", j, ell[j], (long long)dims[modes[j]]);
+  // workspace: status | y64 of every mode | q64 of every mode | partial sums / QR scratch
+  size_t off = align_up(64), y_off[kMaxDims], q_off[kMaxDims], part = ss.ws_bytes;
+  for (int j = 0; j < nmodes; ++j) {
+    y_off[j] = off;
+    off = align_up(off + (size_t)dims[modes[j]] * ell[j] * sizeof(double));
+  }
+  for (int j = 0; j < nmodes; ++j) {
+    q_off[j] = off;
+    off = align_up(off + (size_t)dims[modes[j]] * ell[j] * sizeof(double));
+    part = std::max(part, cholqr_split_bytes(dims[modes[j]], ell[j]));
+  }
+  const size_t part_off = off;
+  off = align_up(off + part);
+  char* ws = nullptr;
+  KRP_TRY(acquire_workspace(&o, off, st, &ws));
+  int* status = o.status_dev ? o.status_dev : reinterpret_cast<int*>(ws);
+  std::string key = "range|dt=" + std::to_string(dtype) + "|p=" + std::to_string(o.prec) +
+                    "|seed=" + std::to_string(o.seed) + "|draw=" + std::to_string(o.draw) +
+                    "|X=" + ptr_key(X) + "|ws=" + ptr_key(ws) + "|st=" + ptr_key(status) + "|";
+  for (int k = 0; k < d; ++k) key += std::to_string(dims[k]) + ",";
+  for (int j = 0; j < nmodes; ++j)
+    key += "|" + std::to_string(modes[j]) + "," + std::to_string(ell[j]) + "," + ptr_key(Q[j]);
+  key += ss.fused ? "|fused" : "";
+  key += (o.flags & KRP_FLAG_MEMO) ? "|memo" : "";
+  const int out_double = dtype == KRP_F64 ? 1 : 0;
+  KRP_TRY(run_maybe_graph(key, !(o.flags & KRP_FLAG_NO_GRAPH), st, [&](hipStream_t cs) -> int {
+    if (!o.status_dev) KRP_TRY(check(launch_fill_int(status, 0, 1, cs), "fill"));
+    double* ys[kMaxDims];
+    for (int j = 0; j < nmodes; ++j) ys[j] = reinterpret_cast<double*>(ws + y_off[j]);
+    void* pw = ws + part_off;
+    if (ss.fused) {
+      KRP_TRY(check(launch_fused(ss.fplan, ss.pb, nmodes, pw, ys, nullptr, 0, cs), "fused sketch"));
+    } else {
+      for (int j = 0; j < nmodes; ++j)
+        KRP_TRY(check(launch_sketch(ss.pb[j], ss.pl[j], pw, ys[j], nullptr, 0, cs), "sketch"));
+    }
+    for (int j = 0; j < nmodes; ++j)
+      KRP_TRY(check(launch_cholqr_split(dims[modes[j]], ell[j], ys[j], reinterpret_cast<double*>(ws + q_off[j]),
+                                        Q[j], out_double, pw, status, cs),
+                    "cholqr"));
+    return KRP_OK;
+  }));
+  if (!o.status_dev) return finish_status(status, st);
+  return KRP_OK;
+}
+
 int krp_hosvd(const void* X, int dtype, int d, const int64_t* dims, const int32_t* rank,
               int32_t oversample, const krp_opts* opts, void* core, void* const* Q, int64_t* core_dims,
               void* stream) {

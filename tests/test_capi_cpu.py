@@ -40,7 +40,7 @@ def test_opts_default(L):
 
 
 def test_status_strings(L):
-    for code in range(7):
+    for code in range(8):
         assert L.krp_status_string(code).decode().startswith("KRP_")
     assert "libkrp" in L.krp_version().decode()
 
@@ -206,3 +206,89 @@ def test_sketch_noalloc_rejects_sketches_beyond_its_array(L):
                               _capi.i32_array((64,)), ctypes.byref(o), _capi.ptr_array([FAKE.value]), None)
     assert rc == _capi.KRP_ENOMEM
     assert "partial sums" in L.krp_last_error().decode()
+
+
+def _range(L, dims=(8, 8, 8), modes=(0, 1), ell=(4, 4), Q=(FAKE, FAKE), dtype=1, prec=1):
+    o = _capi.KrpOpts()
+    L.krp_opts_default(ctypes.byref(o))
+    o.prec = prec
+    return L.krp_range_factors(FAKE, dtype, len(dims), _capi.i64_array(dims), len(modes), _capi.i32_array(modes),
+                               _capi.i32_array(ell), ctypes.byref(o), _capi.ptr_array([q.value for q in Q]), None)
+
+
+@pytest.mark.parametrize("kw", [
+    dict(modes=(0, 0)),
+    dict(ell=(4, 9)),               # more columns than the mode has rows
+    dict(ell=(0, 4)),
+    dict(Q=(FAKE, ctypes.c_void_p(0))),
+    dict(dtype=0),                  # fp64 data with fp32 arithmetic
+])
+def test_range_factors_rejects_before_gpu(L, kw):
+    assert _range(L, **kw) == _capi.KRP_EINVAL
+
+
+def _select(L, n=(150, 90), ell=(5, 5), dtype=1, Q=(FAKE, FAKE), idx=(FAKE, FAKE), A=(FAKE, FAKE), nmodes=None):
+    nm = len(n) if nmodes is None else nmodes
+    return L.krp_sensor_select(nm, _capi.i64_array(n), _capi.i32_array(ell), dtype,
+                               _capi.ptr_array([q.value for q in Q]), None,
+                               _capi.ptr_array([v.value for v in idx]), _capi.ptr_array([a.value for a in A]), None)
+
+
+@pytest.mark.parametrize("kw", [
+    dict(dtype=3),
+    dict(nmodes=0),
+    dict(nmodes=9, n=(9,) * 9, ell=(2,) * 9, Q=(FAKE,) * 9, idx=(FAKE,) * 9, A=(FAKE,) * 9),
+    dict(ell=(0, 5)),
+    dict(ell=(5, 91)),              # more sensors than grid points
+    dict(n=(150, 90), ell=(65, 5)),  # beyond the 64-column limit
+    dict(Q=(FAKE, ctypes.c_void_p(0))),
+    dict(idx=(ctypes.c_void_p(0), FAKE)),
+    dict(A=(FAKE, ctypes.c_void_p(0))),
+])
+def test_sensor_select_rejects_before_gpu(L, kw):
+    assert _select(L, **kw) == _capi.KRP_EINVAL
+    assert L.krp_last_error().decode() != ""
+
+
+@pytest.mark.parametrize("kw", [
+    dict(d=0), dict(d=8), dict(snaps=0), dict(ell=(3, 11)), dict(dtype=2), dict(idx_null=True),
+])
+def test_sensor_measure_rejects_before_gpu(L, kw):
+    d = kw.get("d", 2)
+    dims = (12, 10, 9, 8, 7, 6, 5, 4)[:max(d, 1)]
+    ell = kw.get("ell", (3, 4) + (2,) * 6)[:max(d, 1)]
+    idx = [ctypes.c_void_p(0) if kw.get("idx_null") else FAKE] * max(d, 1)
+    rc = L.krp_sensor_measure(FAKE, kw.get("dtype", 1), d, _capi.i64_array(dims), kw.get("snaps", 3),
+                              _capi.i32_array(ell), _capi.ptr_array([v.value for v in idx]), FAKE, None)
+    assert rc == _capi.KRP_EINVAL
+
+
+@pytest.mark.parametrize("kw", [
+    dict(prec=0),                   # fp32 data, fp64 arithmetic: output type mismatch
+    dict(dtype=0, prec=1),
+    dict(prec=7),
+    dict(ell=(13, 4)),
+    dict(a_null=True),
+    dict(snaps=0),
+])
+def test_sensor_reconstruct_rejects_before_gpu(L, kw):
+    o = _capi.KrpOpts()
+    L.krp_opts_default(ctypes.byref(o))
+    o.prec = kw.get("prec", 1)
+    A = [ctypes.c_void_p(0) if kw.get("a_null") else FAKE] * 2
+    rc = L.krp_sensor_reconstruct(FAKE, kw.get("dtype", 1), 2, _capi.i64_array((12, 10)), kw.get("snaps", 3),
+                                  _capi.i32_array(kw.get("ell", (3, 4))), _capi.ptr_array([a.value for a in A]),
+                                  ctypes.byref(o), FAKE, None)
+    assert rc == _capi.KRP_EINVAL
+
+
+def test_sensor_workspace_sizes(L):
+    nb = ctypes.c_size_t(0)
+    assert L.krp_sensor_workspace_size(0, 3, _capi.i64_array((150, 90, 60)), _capi.i32_array((30, 30, 30)), 0, 1,
+                                       ctypes.byref(nb)) == 0
+    assert nb.value >= 8 * 30 * (150 + 90 + 60)
+    assert L.krp_sensor_workspace_size(1, 3, _capi.i64_array((150, 90, 60)), _capi.i32_array((30, 30, 30)), 61, 1,
+                                       ctypes.byref(nb)) == 0
+    assert nb.value >= 4 * 150 * 90 * 30 * 61  # the largest intermediate of the chain
+    assert L.krp_sensor_workspace_size(2, 3, _capi.i64_array((150, 90, 60)), _capi.i32_array((30, 30, 30)), 61, 1,
+                                       ctypes.byref(nb)) == 1
