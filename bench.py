@@ -20,7 +20,10 @@ ell = 17, core decay 0.8, noise 1e-4), resident in HBM before timing starts.
   workloads      the other configurations, measured the same way: the 64^3
                  fp64 HOSVD (latency), the 512^3 STHOSVD mixed vs fp64, the
                  128^4 HOSVD sketches (per mode and fused), the 256-instance
-                 block-Hankel batch (% of the fp32 VALU peak).
+                 block-Hankel batch (% of the fp32 VALU peak), the sensor
+                 placement of Section 6 on a 150 x 90 x 60 grid (training
+                 factors, sensor selection, measurement and reconstruction of
+                 61 test fields, test error) for r = 5..30.
 """
 from __future__ import annotations
 
@@ -57,6 +60,8 @@ def parse():
     ap.add_argument("--no-extras", action="store_true", help="headline workload only")
     ap.add_argument("--pmc-probe", action="store_true",
                     help="only run a 512 MiB copy and the headline sketch launch (for counter runs)")
+    ap.add_argument("--workload", choices=sorted(SINGLE_WORKLOADS),
+                    help="run one secondary workload only and print its results")
     return ap.parse_args()
 
 
@@ -359,7 +364,55 @@ def extra_workloads(stream):
         ms=hms, sketch_gflop=flops / 1e9, tflops=flops / hms / 1e9,
         frac_fp32_valu_peak=flops / hms / 1e9 / FP32_VALU_PEAK_TFLOPS,
         note="whole batch (sketch, QR, completion); flops of the two sketches only")
+    del hd
+    out["sensor_150x90x60"] = sensor_workload(stream)
     return out
+
+
+def sensor_workload(stream):
+    """Section 6 on synthetic flow snapshots: training factors of the three
+    spatial modes (the snapshot mode is not compressed) by RHOSVD-KRP and
+    RHOSVD-KRP-MEMO, sensor selection, then measurement and reconstruction of
+    the test fields, for sensor grids r x r x r."""
+    import torch
+    import paper_2507_23207_amd as krp
+    from synth import WORKLOADS, flow_snapshots_torch
+
+    w = WORKLOADS["sensor_150x90x60"]
+    dims = list(w["dims"])
+    kw = dict(n_modes=w["n_modes"], decay=w["decay"], noise=w["noise"], mode_seed=w["mode_seed"])
+    train = flow_snapshots_torch(dims, w["n_train"], noise_seed=w["train_seed"], **kw)
+    test = flow_snapshots_torch(dims, w["n_test"], test_seed=w["test_seed"], **kw)
+    status = torch.zeros(1, dtype=torch.int32, device="cuda")  # no host synchronisation in the timed calls
+    train_bytes = train.numel() * 4
+    out_bytes = test.numel() * 4
+    rows = []
+    for r in w["ranks"]:
+        ell = [r] * 3
+        t_fac = gpu_ms(lambda: krp.range_factors(train, [0, 1, 2], ell, prec="bf16x3", status=status), 10, stream)
+        t_memo = gpu_ms(lambda: krp.range_factors(train, [0, 1, 2], ell, prec="bf16x3", memo=True,
+                                                  status=status), 10, stream)
+        qs = krp.range_factors(train, [0, 1, 2], ell, prec="bf16x3", memo=True)
+        t_sel = gpu_ms(lambda: krp.sensor_select(qs, status=status), 10, stream)
+        idx, a = krp.sensor_select(qs)
+        t_meas = gpu_ms(lambda: krp.sensor_measure(test, idx), 20, stream)
+        th = krp.sensor_measure(test, idx)
+        out = krp.sensor_reconstruct(th, a)
+        t_rec = gpu_ms(lambda: krp.sensor_reconstruct(th, a, out=out), 20, stream)
+        err = float(torch.linalg.vector_norm((out - test).double()) / torch.linalg.vector_norm(test.double()))
+        rows.append(dict(r=r, sensors=r ** 3, train_factors_ms=t_fac, train_factors_memo_ms=t_memo,
+                         train_gbps_memo=train_bytes / t_memo / 1e6, select_ms=t_sel, measure_ms=t_meas,
+                         reconstruct_ms=t_rec, reconstruct_gbps_written=out_bytes / t_rec / 1e6,
+                         test_rel_err=err))
+    print("[bench] sensor workload done", file=sys.stderr, flush=True)
+    return dict(dims=dims, n_train=w["n_train"], n_test=w["n_test"], by_rank=rows,
+                note="synthetic flow snapshots (Tangaroa stand-in); training tensor fp32 "
+                     f"{train_bytes / 1e6:.0f} MB, 3xbf16 sketches; reconstruction writes "
+                     f"{out_bytes / 1e6:.0f} MB of fp32 fields")
+
+
+# secondary workloads that can run on their own (--workload)
+SINGLE_WORKLOADS = {"sensor_150x90x60": lambda stream: sensor_workload(stream)}
 
 
 def main():
@@ -372,6 +425,9 @@ def main():
 
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream()
+    if args.workload:
+        print(json.dumps({"workload": args.workload, **SINGLE_WORKLOADS[args.workload](stream)}), flush=True)
+        return
     out = headline(args, stream)
     if out is None:
         return

@@ -239,14 +239,15 @@ int krp_sensor_measure(const void* T, int dtype, int d, const int64_t* dims, int
 
 /* Reconstruction of the fields from their sensor values (Section 6):
  *   T_out = T_hat x_1 A_1 x_2 ... x_d A_d   (snapshot mode untouched),
- * on the TTM kernels in natural mode order (the expanding products run in
- * 64-column chunks of each mode).
+ * one mode after the other (smallest expansion dims[i] / ell[i] first), in
+ * the storage precision
+ * (opts->prec is not used): modes with ell[i] <= 64 on an expansion kernel
+ * (vector FMAs; output-bound), wider ones on the TTM kernels in 64-column
+ * chunks of the output mode.
  *   T_hat  device, ell[0] x ... x ell[d-1] x snapshots, `dtype`
  *   A      host array of d device pointers, A[i] dims[i] x ell[i] column-major
  *   T_out  device, dims[0] x ... x dims[d-1] x snapshots
- *   opts->prec  KRP_P_FP64 for fp64 data; fp32 data: KRP_P_FP32, KRP_P_BF16
- *          or KRP_P_BF16X3 (the factors are taken in fp64 and cast to the
- *          arithmetic type) */
+ *   opts   may be NULL (workspace and graph flags only) */
 int krp_sensor_reconstruct(const void* T_hat, int dtype, int d, const int64_t* dims, int64_t snapshots,
                            const int32_t* ell, const void* const* A, const krp_opts* opts, void* T_out,
                            void* stream);

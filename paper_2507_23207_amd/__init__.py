@@ -249,9 +249,9 @@ def sensor_measure(t, idx):
     return out
 
 
-def sensor_reconstruct(t_hat, a, prec=None, graph=True, out=None):
-    """T_hat x_1 A_1 ... x_d A_d (snapshot mode last, untouched);
-    krp_sensor_reconstruct.  ``prec`` defaults to the storage precision."""
+def sensor_reconstruct(t_hat, a, graph=True, out=None):
+    """T_hat x_1 A_1 ... x_d A_d (snapshot mode last, untouched), in the
+    storage precision; krp_sensor_reconstruct."""
     torch = _torch()
     _check_tensor(t_hat)
     d = len(a)
@@ -263,8 +263,6 @@ def sensor_reconstruct(t_hat, a, prec=None, graph=True, out=None):
         _check_colmajor(m, dims[j], ell[j], t_hat.dtype, f"A[{j}]")
         if ell[j] != t_hat.shape[j]:
             raise ValueError(f"A[{j}] has {ell[j]} columns, t_hat mode {j} has {t_hat.shape[j]} entries")
-    if prec is None:
-        prec = "fp64" if t_hat.dtype == torch.float64 else "fp32"
     snaps = int(t_hat.shape[d])
     if out is None:
         out = empty_kolda(dims + [snaps], t_hat.dtype, t_hat.device)
@@ -272,7 +270,7 @@ def sensor_reconstruct(t_hat, a, prec=None, graph=True, out=None):
         raise ValueError("out has the wrong shape or dtype")
     else:
         _check_tensor(out)
-    o, _, keep = _opts(prec, 0, 0, graph=graph)
+    o, _, keep = _opts("fp32", 0, 0, graph=graph)
     rc = _capi.lib().krp_sensor_reconstruct(ctypes.c_void_p(t_hat.data_ptr()), _dtype_code(t_hat), d,
                                             _capi.i64_array(dims), snaps, _capi.i32_array(ell),
                                             _capi.ptr_array([m.data_ptr() for m in a]), ctypes.byref(o),

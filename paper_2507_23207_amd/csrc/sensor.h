@@ -36,6 +36,23 @@ struct SensorMeasureArgs {
   int64_t total;  // prod(ell) * snapshots
 };
 
+// One mode of the reconstruction: out (P x N x Q) = g (P x ell x Q) x_2 A,
+// A N x ell column-major; storage type for g, A and out.
+constexpr int kExpandMaxEll = 64;
+constexpr int kExpandLds = 32768;   // bytes of A rows staged per workgroup (P > 1)
+constexpr int kExpandRowsQ = 32;    // values of q per workgroup (P == 1)
+struct SensorExpandArgs {
+  const void* g;
+  const void* a;
+  void* out;
+  int64_t p, n, q;
+  int ell;
+  // set by the launcher
+  int cc;
+  int64_t p_tiles, items;
+};
+hipError_t launch_sensor_expand(const SensorExpandArgs& e, int is_double, hipStream_t st);
+
 size_t sensor_pivot_lds(int ell_max);
 hipError_t launch_sensor_select(const SensorSelectArgs& a, int q_is_double, hipStream_t st);
 hipError_t launch_sensor_measure(const SensorMeasureArgs& a, int is_double, hipStream_t st);

@@ -265,7 +265,119 @@ __global__ __launch_bounds__(256) void sensor_transpose_kernel(const void* A, in
   At[e] = (double)reinterpret_cast<const T*>(A)[j + n * k];
 }
 
+// Expansion T x_i A of one mode (a reduction of length ell <= LMAX, an output
+// mode of N >= ell): out[p, c, q] = sum_a A[c, a] g[p, a, q] for g viewed as
+// P x ell x Q and out as P x N x Q.  Output-bound: the products run on the
+// vector ALUs in the storage precision.
+//
+// P > 1: a wave owns 64 consecutive p of one q and holds g[p, :, q] in
+// registers (zero past ell); the block's chunk of A rows sits in LDS as
+// [c][a] and every lane reads the same entry (broadcast); loads of g and
+// stores of out are coalesced along p.
+template <typename T, int LMAX>
+__global__ __launch_bounds__(256) void sensor_expand_cols_kernel(SensorExpandArgs e) {
+  __shared__ T As[kExpandLds / sizeof(T)];
+  const int c0 = blockIdx.y * e.cc;
+  const int cn = (int)min<int64_t>(e.cc, e.n - c0);
+  const T* A = reinterpret_cast<const T*>(e.a);
+  for (int i = threadIdx.x; i < cn * LMAX; i += 256) {
+    const int c = i / LMAX, a = i % LMAX;
+    As[i] = a < e.ell ? A[(c0 + c) + e.n * a] : (T)0;
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63;
+  const int64_t item = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (item >= e.items) return;
+  const int64_t q = item / e.p_tiles;
+  const int64_t p = (item % e.p_tiles) * 64 + lane;
+  if (p >= e.p) return;
+  const T* g = reinterpret_cast<const T*>(e.g) + p + e.p * e.ell * q;
+  T gv[LMAX];
+#pragma unroll
+  for (int a = 0; a < LMAX; ++a) gv[a] = a < e.ell ? g[e.p * a] : (T)0;
+  T* out = reinterpret_cast<T*>(e.out) + p + e.p * (c0 + e.n * q);
+  // four output rows at a time: independent sums keep the LDS reads in flight
+  int c = 0;
+  for (; c + 3 < cn; c += 4) {
+    T acc[4] = {0, 0, 0, 0};
+#pragma unroll
+    for (int a = 0; a < LMAX; ++a)
+#pragma unroll
+      for (int u = 0; u < 4; ++u) acc[u] += As[(c + u) * LMAX + a] * gv[a];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) out[e.p * (c + u)] = acc[u];
+  }
+  for (; c < cn; ++c) {
+    T acc = 0;
+#pragma unroll
+    for (int a = 0; a < LMAX; ++a) acc += As[c * LMAX + a] * gv[a];
+    out[e.p * c] = acc;
+  }
+}
+
+// P == 1 (mode 1 of the tensor): out[c + N q] = sum_a A[c, a] g[a + ell q].
+// A workgroup owns 256 consecutive c (rows of A in registers) and a block of
+// kExpandRowsQ values of q, whose columns of g it stages in LDS with
+// coalesced loads; every lane then reads the same LDS entry (broadcast) and
+// the stores are coalesced along c.
+template <typename T, int LMAX>
+__global__ __launch_bounds__(256) void sensor_expand_rows_kernel(SensorExpandArgs e) {
+  constexpr int QB = kExpandRowsQ;
+  __shared__ T gs[QB * LMAX];
+  const int64_t q0 = (int64_t)blockIdx.x * QB;
+  const int qn = (int)min<int64_t>(QB, e.q - q0);
+  const T* g = reinterpret_cast<const T*>(e.g) + e.ell * q0;
+  for (int i = threadIdx.x; i < QB * LMAX; i += blockDim.x) {
+    const int qq = i / LMAX, a = i % LMAX;
+    gs[i] = (qq < qn && a < e.ell) ? g[a + e.ell * qq] : (T)0;
+  }
+  const int64_t c = (int64_t)blockIdx.y * blockDim.x + threadIdx.x;
+  const bool cv = c < e.n;
+  const T* A = reinterpret_cast<const T*>(e.a);
+  T ar[LMAX];
+#pragma unroll
+  for (int a = 0; a < LMAX; ++a) ar[a] = (cv && a < e.ell) ? A[c + e.n * a] : (T)0;
+  __syncthreads();
+  if (!cv) return;
+  T* out = reinterpret_cast<T*>(e.out) + c + e.n * q0;
+  for (int qq = 0; qq < qn; ++qq) {
+    T acc = 0;
+#pragma unroll
+    for (int a = 0; a < LMAX; ++a) acc += ar[a] * gs[qq * LMAX + a];
+    out[e.n * qq] = acc;
+  }
+}
+
+template <typename T, int LMAX>
+hipError_t expand_go(SensorExpandArgs e, hipStream_t st) {
+  if (e.p > 1) {
+    e.cc = (int)std::min<int64_t>(e.n, kExpandLds / (LMAX * sizeof(T)));
+    e.p_tiles = (e.p + 63) / 64;
+    e.items = e.p_tiles * e.q;
+    const dim3 grid((unsigned)((e.items + 3) / 4), (unsigned)((e.n + e.cc - 1) / e.cc));
+    hipLaunchKernelGGL((sensor_expand_cols_kernel<T, LMAX>), grid, dim3(256), 0, st, e);
+  } else {
+    const dim3 grid((unsigned)((e.q + kExpandRowsQ - 1) / kExpandRowsQ), (unsigned)((e.n + 255) / 256));
+    hipLaunchKernelGGL((sensor_expand_rows_kernel<T, LMAX>), grid, dim3(256), 0, st, e);
+  }
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t expand_dispatch(const SensorExpandArgs& e, hipStream_t st) {
+  if (e.ell <= 8) return expand_go<T, 8>(e, st);
+  if (e.ell <= 16) return expand_go<T, 16>(e, st);
+  if (e.ell <= 32) return expand_go<T, 32>(e, st);
+  return expand_go<T, 64>(e, st);
+}
+
 }  // namespace
+
+hipError_t launch_sensor_expand(const SensorExpandArgs& e, int is_double, hipStream_t st) {
+  if (e.ell < 1 || e.ell > kExpandMaxEll || e.n < 1) return hipErrorInvalidValue;
+  if (e.p * e.q == 0) return hipSuccess;
+  return is_double ? expand_dispatch<double>(e, st) : expand_dispatch<float>(e, st);
+}
 
 size_t sensor_pivot_lds(int ell_max) { return (size_t)ell_max * (2 * ell_max + 1) * sizeof(double); }
 

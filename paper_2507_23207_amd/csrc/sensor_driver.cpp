@@ -69,20 +69,29 @@ struct ReconLayout {
   int64_t elems_max;
 };
 
-// Sizes of the reconstruction chain: mode i expands ell_i -> dims_i in
-// natural order; the last step writes the caller's output.
+// Order of the reconstruction chain: smallest expansion dims_i / ell_i first
+// (ties: lower mode first), so the intermediate tensors stay small and the
+// widest expansion produces the output.  Any order gives the same product.
+void recon_order(int d, const int64_t* dims, const int32_t* ell, int* order) {
+  for (int i = 0; i < d; ++i) order[i] = i;
+  std::stable_sort(order, order + d, [&](int a, int b) { return dims[a] * ell[b] < dims[b] * ell[a]; });
+}
+// Sizes of the reconstruction chain (mode order[s] expands ell -> dims at
+// step s); the last step writes the caller's output.
 ReconLayout recon_layout(int d, const int64_t* dims, const int32_t* ell, int64_t snaps, size_t esz) {
   ReconLayout l{};
   size_t off = 0;
-  for (int i = 0; i < d; ++i) {
+  for (int i = 0; i < d; ++i) {  // fp64 transposed factors of the modes that take the TTM path
     l.at[i] = off;
-    off = align_up(off + (size_t)dims[i] * ell[i] * sizeof(double));
+    if (ell[i] > kExpandMaxEll) off = align_up(off + (size_t)dims[i] * ell[i] * sizeof(double));
   }
+  int order[kMaxDims];
+  recon_order(d, dims, ell, order);
   int64_t cur[kMaxDims];
   for (int i = 0; i < d; ++i) cur[i] = ell[i];
   l.elems_max = 0;
-  for (int i = 0; i + 1 < d; ++i) {
-    cur[i] = dims[i];
+  for (int s = 0; s + 1 < d; ++s) {
+    cur[order[s]] = dims[order[s]];
     int64_t e = snaps;
     for (int k = 0; k < d; ++k) e *= cur[k];
     l.elems_max = std::max(l.elems_max, e);
@@ -188,10 +197,6 @@ int krp_sensor_reconstruct(const void* T_hat, int dtype, int d, const int64_t* d
   if (!T_hat || !T_out || !A) return set_error(KRP_EINVAL, "T_hat, T_out and A must not be NULL");
   for (int i = 0; i < d; ++i)
     if (!A[i]) return set_error(KRP_EINVAL, "A[%d] is NULL", i);
-  if (o.prec < KRP_P_FP64 || o.prec > KRP_P_BF16X3) return set_error(KRP_EINVAL, "unknown precision %d", o.prec);
-  if (dtype == KRP_F64 && o.prec != KRP_P_FP64) return set_error(KRP_EINVAL, "fp64 data requires KRP_P_FP64");
-  if (dtype == KRP_F32 && o.prec == KRP_P_FP64)
-    return set_error(KRP_EINVAL, "fp32 data is reconstructed in fp32, bf16 or 3xbf16 (opts->prec)");
   const bool x64 = dtype == KRP_F64;
   const size_t esz = x64 ? 8 : 4;
   const ReconLayout l = recon_layout(d, dims, ell, snapshots, esz);
@@ -199,25 +204,44 @@ int krp_sensor_reconstruct(const void* T_hat, int dtype, int d, const int64_t* d
   char* ws = nullptr;
   rc = acquire_workspace(&o, l.total, st, &ws);
   if (rc != KRP_OK) return rc;
-  std::string key = "sensor_recon|dt=" + std::to_string(dtype) + "|p=" + std::to_string(o.prec) + "|s=" +
+  std::string key = "sensor_recon|dt=" + std::to_string(dtype) + "|s=" +
                     std::to_string(snapshots) + "|in=" + ptr_key(T_hat) + "|out=" + ptr_key(T_out) +
                     "|ws=" + ptr_key(ws);
   for (int i = 0; i < d; ++i)
     key += "|" + std::to_string(dims[i]) + "," + std::to_string(ell[i]) + "," + ptr_key(A[i]);
   return run_maybe_graph(key, !(o.flags & KRP_FLAG_NO_GRAPH), st, [&](hipStream_t cs) -> int {
-    for (int i = 0; i < d; ++i) {
-      const hipError_t e = launch_sensor_transpose(A[i], x64 ? 1 : 0, dims[i], ell[i],
-                                                   reinterpret_cast<double*>(ws + l.at[i]), cs);
-      if (e != hipSuccess) return hip_fail(e, "sensor transpose kernel");
-    }
+    int order[kMaxDims];
+    recon_order(d, dims, ell, order);
     int64_t cur[kMaxDims];
     for (int i = 0; i < d; ++i) cur[i] = ell[i];
     cur[d] = snapshots;
     const void* in = T_hat;
-    for (int i = 0; i < d; ++i) {
-      char* out = i + 1 == d ? reinterpret_cast<char*>(T_out) : ws + l.buf[i & 1];
+    for (int s = 0; s < d; ++s) {
+      const int i = order[s];
+      char* out = s + 1 == d ? reinterpret_cast<char*>(T_out) : ws + l.buf[s & 1];
       int64_t before = 1;  // elements of the modes ahead of mode i (already expanded)
       for (int k = 0; k < i; ++k) before *= cur[k];
+      int64_t after = 1;
+      for (int k = i + 1; k <= d; ++k) after *= cur[k];
+      if (ell[i] <= kExpandMaxEll) {
+        SensorExpandArgs ea{};
+        ea.g = in;
+        ea.a = A[i];
+        ea.out = out;
+        ea.p = before;
+        ea.n = dims[i];
+        ea.q = after;
+        ea.ell = ell[i];
+        const hipError_t e = launch_sensor_expand(ea, x64 ? 1 : 0, cs);
+        if (e != hipSuccess) return hip_fail(e, "sensor expansion kernel");
+        cur[i] = dims[i];
+        in = out;
+        continue;
+      }
+      // wider reductions: TTM with the factor transposed to fp64, 64 output columns at a time
+      double* at = reinterpret_cast<double*>(ws + l.at[i]);
+      hipError_t e = launch_sensor_transpose(A[i], x64 ? 1 : 0, dims[i], ell[i], at, cs);
+      if (e != hipSuccess) return hip_fail(e, "sensor transpose kernel");
       for (int64_t c0 = 0; c0 < dims[i]; c0 += kTtmChunk) {
         TtmProblem tp;
         tp.g = in;
@@ -226,12 +250,12 @@ int krp_sensor_reconstruct(const void* T_hat, int dtype, int d, const int64_t* d
         for (int k = 0; k <= d; ++k) tp.dims[k] = cur[k];
         tp.mode = i;
         tp.ell = (int)std::min<int64_t>(kTtmChunk, dims[i] - c0);
-        tp.prec = o.prec;
-        tp.q64 = reinterpret_cast<const double*>(ws + l.at[i]) + (size_t)ell[i] * c0;
+        tp.prec = x64 ? KRP_P_FP64 : KRP_P_FP32;
+        tp.q64 = at + (size_t)ell[i] * c0;
         tp.out = out + (size_t)(c0 * before) * esz;
         tp.out_is_double = x64 ? 1 : 0;
         tp.out_ld = dims[i];
-        const hipError_t e = launch_ttm(tp, cs);
+        e = launch_ttm(tp, cs);
         if (e != hipSuccess) return hip_fail(e, "sensor reconstruction ttm");
       }
       cur[i] = dims[i];

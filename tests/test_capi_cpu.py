@@ -264,9 +264,7 @@ def test_sensor_measure_rejects_before_gpu(L, kw):
 
 
 @pytest.mark.parametrize("kw", [
-    dict(prec=0),                   # fp32 data, fp64 arithmetic: output type mismatch
-    dict(dtype=0, prec=1),
-    dict(prec=7),
+    dict(dtype=5),
     dict(ell=(13, 4)),
     dict(a_null=True),
     dict(snaps=0),
