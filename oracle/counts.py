@@ -71,3 +71,32 @@ def table1_flops(method, d, n, ell):
         "RSTHOSVD": 4 * n ** d * ell,
         "RSTHOSVD-KRP": 4 * n ** d * ell,
     }[method]
+
+
+def rhosvd_dense_count(dims, ells):
+    """RHOSVD baseline: a dense prod_{j != i} n_j x ell_i Gaussian per mode."""
+    total = 0
+    for i in range(len(dims)):
+        k = 1
+        for j, n in enumerate(dims):
+            if j != i:
+                k *= n
+        total += k * ells[i]
+    return total
+
+
+def rsthosvd_dense_count(dims, ells, order=None):
+    """RSTHOSVD baseline: mode i's dense Gaussian has one row per column of the
+    current core's unfolding (compressed modes at ell_j)."""
+    d = len(dims)
+    order = list(range(d)) if order is None else list(order)
+    cur = list(dims)
+    total = 0
+    for i in order:
+        k = 1
+        for j in range(d):
+            if j != i:
+                k *= cur[j]
+        total += k * ells[i]
+        cur[i] = ells[i]
+    return total

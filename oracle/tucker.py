@@ -1,4 +1,5 @@
-"""Oracle Tucker algorithms: Algorithms 4, 5, 7, 8, memoised HOSVD, truncation.
+"""Oracle Tucker algorithms: Algorithms 4, 5, 7, 8, memoised HOSVD, the
+dense-Gaussian RHOSVD / RSTHOSVD baselines of Section 5.3, truncation.
 
 TEST INFRASTRUCTURE ONLY (see the package docstring).  Parity: pinned by
 exact recovery of exactly low-multilinear-rank tensors, by the HOSVD error
@@ -22,6 +23,10 @@ from .linalg import leading_left_singular_vectors, qr_pos
 from .tensor import frob, mttkrp, multi_ttm, ttm, unfold
 
 MEMO_SKETCH = 0xFFFF
+# Factor id of the dense Gaussian matrices of the RHOSVD / RSTHOSVD baselines
+# (Section 5.3): for mode i, Omega_i has one row per column of the unfolding
+# X_(i) (its Kolda column index) and ell_i columns, drawn under sketch id i.
+DENSE_FACTOR = 0xFFFE
 
 
 def sketch_factors(seed, draw, sketch, cur_shape, ell, mode):
@@ -67,6 +72,47 @@ def rsthosvd_krp(x, ranks, p, seed=2507, draw=0, order=None, return_sketches=Fal
         ell = ranks[i] + p
         f = sketch_factors(seed, draw, i, g.shape, ell, i)
         y = mttkrp(g, f, i)
+        ys[i] = y
+        qs[i] = qr_pos(y)[0]
+        g = ttm(g, qs[i].T, i)
+    return (g, qs, ys) if return_sketches else (g, qs)
+
+
+def dense_omega(seed, draw, mode, rows, ell):
+    """The dense Gaussian matrix of a baseline sketch of ``mode``: rows x ell."""
+    return rng.factor(seed, draw, mode, DENSE_FACTOR, rows, ell)
+
+
+def rhosvd_gauss(x, ranks, p, seed=2507, draw=0, return_sketches=False):
+    """Randomized HOSVD with dense Gaussian matrices (the RHOSVD baseline of
+    Section 5.3): Y_i = X_(i) Omega_i with Omega_i of size prod_{j != i} n_j x
+    ell_i, thin QR, then the core as in Algorithm 7."""
+    x = np.asarray(x, dtype=np.float64)
+    d = x.ndim
+    qs, ys = [], []
+    for i in range(d):
+        ell = ranks[i] + p
+        xi = unfold(x, i)
+        y = xi @ dense_omega(seed, draw, i, xi.shape[1], ell)
+        ys.append(y)
+        qs.append(qr_pos(y)[0])
+    g = multi_ttm(x, qs, transpose=True)
+    return (g, qs, ys) if return_sketches else (g, qs)
+
+
+def rsthosvd_gauss(x, ranks, p, seed=2507, draw=0, order=None, return_sketches=False):
+    """Randomized STHOSVD with dense Gaussian matrices (the RSTHOSVD baseline):
+    the sketch of mode i is G_(i) Omega_i for the current core G."""
+    x = np.asarray(x, dtype=np.float64)
+    d = x.ndim
+    order = list(range(d)) if order is None else list(order)
+    g = x
+    qs = [None] * d
+    ys = [None] * d
+    for i in order:
+        ell = ranks[i] + p
+        gi = unfold(g, i)
+        y = gi @ dense_omega(seed, draw, i, gi.shape[1], ell)
         ys[i] = y
         qs[i] = qr_pos(y)[0]
         g = ttm(g, qs[i].T, i)

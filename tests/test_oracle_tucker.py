@@ -197,3 +197,82 @@ def test_era_rng_percentages(golden_dir):
     assert [m * s, n * s] == gold["printed"]["problem_size"]
     assert math.floor(1000 * krp / randera) / 10 == gold["printed"]["krp_over_randera_percent_approx"]
     assert math.floor(1000 * krp / dense) / 10 == gold["printed"]["krp_over_rgauss_percent_about"]
+
+
+def test_dense_baseline_sketch_matches_loops():
+    """Y_i = X_(i) Omega_i: row k of Omega_i multiplies the fibre whose other
+    indices have Kolda index k (modes after i counted past those before it)."""
+    import itertools
+    x = low_rank_tensor((3, 4, 2, 3), (2, 2, 2, 2), noise=0.1, seed=11)
+    _, _, ys = tucker.rhosvd_gauss(x, (2, 2, 2, 2), 1, seed=5, return_sketches=True)
+    for i in range(4):
+        others = [j for j in range(4) if j != i]
+        kdim = int(np.prod([x.shape[j] for j in others]))
+        om = tucker.dense_omega(5, 0, i, kdim, 3)
+        want = np.zeros((x.shape[i], 3))
+        for idx in itertools.product(*[range(n) for n in x.shape]):
+            k, s = 0, 1
+            for j in others:
+                k += idx[j] * s
+                s *= x.shape[j]
+            want[idx[i]] += x[idx] * om[k]
+        assert np.allclose(ys[i], want, atol=1e-12)
+
+
+@pytest.mark.parametrize("fn", ["rhosvd_gauss", "rsthosvd_gauss"])
+def test_dense_baselines_recover_exactly(fn):
+    x = _exact((9, 8, 10), (3, 2, 4))
+    g, qs = getattr(tucker, fn)(x, (3, 2, 4), 2, seed=8)
+    assert tucker.tucker_rel_error(x, g, qs) <= 1e-12
+
+
+def test_dense_baseline_counts_match_table1(monkeypatch):
+    """Entries drawn by the baselines: ell d n^(d-1) (RHOSVD) and, for RSTHOSVD,
+    ell^i n^(d-i) while processing mode i (Section 5.1; Table 1 keeps the
+    leading term ell n^(d-1))."""
+    d, n, ell = 4, 6, 3
+    dims = [n] * d
+    assert counts.rhosvd_dense_count(dims, [ell] * d) == counts.table1_rng("RHOSVD", d, n, ell)
+    st = counts.rsthosvd_dense_count(dims, [ell] * d)
+    assert st == sum(ell ** i * n ** (d - i) for i in range(1, d + 1))
+    assert st - counts.table1_rng("RSTHOSVD", d, n, ell) == sum(ell ** i * n ** (d - i) for i in range(2, d + 1))
+    drawn = []
+    real = tucker.rng.factor
+
+    def spy(seed, draw, sketch, f, rows, cols, instance=0):
+        assert f == tucker.DENSE_FACTOR
+        drawn.append(rows * cols)
+        return real(seed, draw, sketch, f, rows, cols, instance)
+
+    monkeypatch.setattr(tucker.rng, "factor", spy)
+    x = low_rank_tensor(dims, (2,) * d, noise=0.0, seed=7)
+    tucker.rhosvd_gauss(x, (2,) * d, 1)
+    assert sum(drawn) == counts.rhosvd_dense_count(dims, [ell] * d)
+    drawn.clear()
+    tucker.rsthosvd_gauss(x, (2,) * d, 1)
+    assert sum(drawn) == counts.rsthosvd_dense_count(dims, [ell] * d)
+
+
+def test_cauchy_errors_comparable_to_hosvd():
+    """Section 5.3 on a small Cauchy tensor (alpha = 2, no oversampling): the
+    randomized variants, KRP or dense Gaussian, are never better than the
+    deterministic HOSVD / STHOSVD and stay within the same order of magnitude
+    (a single draw without oversampling; the paper plots a log scale), and
+    every method's error falls with the rank."""
+    from synth import cauchy_tensor
+    x = cauchy_tensor((24, 24, 24, 24), alpha=2.0)
+    hos = {"krp": tucker.rhosvd_krp, "memo": tucker.rhosvd_krp_memo, "gauss": tucker.rhosvd_gauss}
+    sts = {"krp": tucker.rsthosvd_krp, "gauss": tucker.rsthosvd_gauss}
+    prev = {}
+    for r in (2, 4, 6):
+        ranks = (r,) * 4
+        e_det = tucker.tucker_rel_error_identity(x, tucker.hosvd(x, ranks)[0])
+        e_std = tucker.tucker_rel_error_identity(x, tucker.sthosvd(x, ranks)[0])
+        for kind, fns, ref in (("h", hos, e_det), ("s", sts, e_std)):
+            for name, fn in fns.items():
+                e = tucker.tucker_rel_error_identity(x, fn(x, ranks, 0, seed=3)[0])
+                assert ref <= e * (1 + 1e-9) and e <= 25 * ref, (kind, name, r, e, ref)
+                key = kind + name
+                if key in prev:
+                    assert e < prev[key]
+                prev[key] = e
