@@ -85,7 +85,7 @@ enum {
                               tuning is skipped while the stream is being captured.  The
                               tiling changes only the order of the fp64 reduction of partial
                               sums, i.e. results at the rounding level. */
-  KRP_FLAG_MEMO = 4        /* RHOSVD-KRP-MEMO (Section 5.1, Table 1): one shared factor set for
+  KRP_FLAG_MEMO = 4,       /* RHOSVD-KRP-MEMO (Section 5.1, Table 1): one shared factor set for
                               all modes.  Factor j is drawn once with max(ell) columns under
                               sketch id 0xFFFF (counter word 2 bits 16..31) and factor id j; the
                               sketch of mode i uses the first ell_i columns of every other
@@ -94,6 +94,16 @@ enum {
                               all-mode pass over X then computes the product of a slab with
                               the shared mode-2 factor once for mode 1 and every outer mode
                               (the memoised partial MTTKRP). */
+  KRP_FLAG_GAUSSIAN = 8    /* the dense-Gaussian baselines of Section 5.3 (RHOSVD, RSTHOSVD):
+                              the sketch of mode i is X_(i) Omega_i with a dense Gaussian Omega_i
+                              of prod_{j != i} n_j rows (current sizes in krp_sthosvd) and ell_i
+                              columns; entry (k, c) is the factor entry (row k, column c) of
+                              sketch id i, factor id 0xFFFE, k the Kolda index of the other
+                              modes.  Omega_i is drawn into the workspace, X unfolded into a
+                              copy for modes after the first, and Y formed by a split-K product
+                              on the matrix cores: workspaces grow by about K_i ell_i + N
+                              elements (krp_workspace_size which 3..5).  Not with
+                              KRP_FLAG_MEMO; KRP_FLAG_AUTOTUNE does not apply. */
 };
 
 typedef struct krp_opts {
@@ -260,8 +270,8 @@ int krp_sensor_workspace_size(int which, int d, const int64_t* dims, const int32
 
 /* Device workspace a call with the same arguments needs when the caller
  * provides opts->workspace.  `which`: 0 sketch (rank[] = ell[] per listed
- * mode, nmodes = d, modes 0..d-1), 1 hosvd, 2 sthosvd.  Returns KRP_OK and
- * writes *bytes, or KRP_EINVAL. */
+ * mode, nmodes = d, modes 0..d-1), 1 hosvd, 2 sthosvd; 3, 4, 5 the same with
+ * KRP_FLAG_GAUSSIAN.  Returns KRP_OK and writes *bytes, or KRP_EINVAL. */
 int krp_workspace_size(int which, int dtype, int d, const int64_t* dims, const int32_t* rank,
                        int32_t oversample, int prec, size_t* bytes);
 int krp_hankel_workspace_size(int batch, const int64_t* s, int m, int n, int r, int ell_r,

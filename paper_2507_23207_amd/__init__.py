@@ -67,7 +67,7 @@ def _stream(x):
 
 
 def _opts(prec, seed, draw, truncate=False, graph=True, order=None, workspace=None,
-          status=None, want_err=False, autotune=False, memo=False):
+          status=None, want_err=False, autotune=False, memo=False, gaussian=False):
     o = _capi.KrpOpts()
     _capi.lib().krp_opts_default(ctypes.byref(o))
     o.seed = int(seed)
@@ -75,7 +75,7 @@ def _opts(prec, seed, draw, truncate=False, graph=True, order=None, workspace=No
     o.prec = PREC[prec] if isinstance(prec, str) else int(prec)
     o.truncate = 1 if truncate else 0
     o.flags = ((0 if graph else _capi.KRP_FLAG_NO_GRAPH) | (_capi.KRP_FLAG_AUTOTUNE if autotune else 0)
-               | (_capi.KRP_FLAG_MEMO if memo else 0))
+               | (_capi.KRP_FLAG_MEMO if memo else 0) | (_capi.KRP_FLAG_GAUSSIAN if gaussian else 0))
     keep = []
     if order is not None:
         arr = _capi.i32_array(order)
@@ -100,18 +100,21 @@ def _check_tensor(x):
         raise ValueError("tensor must have Kolda (column-major) strides; use kolda(x)")
 
 
-def sketch(x, modes, ell, prec="fp32", seed=2507, draw=0, graph=True, autotune=False, memo=False):
+def sketch(x, modes, ell, prec="fp32", seed=2507, draw=0, graph=True, autotune=False, memo=False,
+           gaussian=False):
     """KRP sketches Y_j = X_(m_j) (KRP of the other factors); krp_sketch.
 
     ``autotune``: time the candidate tilings on first use of each shape and keep
     the fastest (KRP_FLAG_AUTOTUNE; cached in $KRP_TUNE_CACHE).  ``memo``: one
-    shared factor set for all modes (KRP_FLAG_MEMO, Section 5.1)."""
+    shared factor set for all modes (KRP_FLAG_MEMO, Section 5.1).  ``gaussian``:
+    dense Gaussian sketches, the RHOSVD baseline of Section 5.3
+    (KRP_FLAG_GAUSSIAN)."""
     torch = _torch()
     _check_tensor(x)
     modes = [int(m) for m in modes]
     ell = [int(v) for v in ell] if hasattr(ell, "__len__") else [int(ell)] * len(modes)
     ys = [torch.empty((l, x.shape[m]), dtype=x.dtype, device=x.device).t() for m, l in zip(modes, ell)]
-    o, _, keep = _opts(prec, seed, draw, graph=graph, autotune=autotune, memo=memo)
+    o, _, keep = _opts(prec, seed, draw, graph=graph, autotune=autotune, memo=memo, gaussian=gaussian)
     rc = _capi.lib().krp_sketch(ctypes.c_void_p(x.data_ptr()), _dtype_code(x), x.dim(),
                                 _capi.i64_array(x.shape), len(modes), _capi.i32_array(modes),
                                 _capi.i32_array(ell), ctypes.byref(o),
@@ -141,7 +144,7 @@ def sketch_noalloc(x, modes, ell, ys, prec="fp32", seed=2507, draw=0):
 
 
 def _tucker(fn, x, ranks, oversample, prec, seed, draw, truncate, rel_err, graph, order,
-            workspace, status, autotune=False, memo=False):
+            workspace, status, autotune=False, memo=False, gaussian=False):
     _check_tensor(x)
     d = x.dim()
     ranks = [int(r) for r in ranks]
@@ -149,7 +152,7 @@ def _tucker(fn, x, ranks, oversample, prec, seed, draw, truncate, rel_err, graph
     core = empty_kolda(ells, x.dtype, x.device)
     qs = [_torch().empty((l, n), dtype=x.dtype, device=x.device).t() for n, l in zip(x.shape, ells)]
     o, err, keep = _opts(prec, seed, draw, truncate, graph, order, workspace, status, rel_err, autotune,
-                         memo)
+                         memo, gaussian)
     cdims = (ctypes.c_int64 * d)()
     rc = fn(ctypes.c_void_p(x.data_ptr()), _dtype_code(x), d, _capi.i64_array(x.shape),
             _capi.i32_array(ranks), int(oversample), ctypes.byref(o), ctypes.c_void_p(core.data_ptr()),
@@ -166,19 +169,22 @@ def _tucker(fn, x, ranks, oversample, prec, seed, draw, truncate, rel_err, graph
 
 
 def hosvd(x, ranks, oversample, prec="fp32", seed=2507, draw=0, truncate=False, rel_err=False,
-          graph=True, workspace=None, status=None, autotune=False, memo=False):
+          graph=True, workspace=None, status=None, autotune=False, memo=False, gaussian=False):
     """Randomized HOSVD with KRPs (Algorithm 7); krp_hosvd.  Returns (core, [Q_i], rel_err).
 
-    ``memo``: RHOSVD-KRP-MEMO, one shared factor set for all modes (KRP_FLAG_MEMO)."""
+    ``memo``: RHOSVD-KRP-MEMO, one shared factor set for all modes (KRP_FLAG_MEMO).
+    ``gaussian``: the dense-Gaussian RHOSVD baseline (KRP_FLAG_GAUSSIAN)."""
     return _tucker(_capi.lib().krp_hosvd, x, ranks, oversample, prec, seed, draw, truncate, rel_err,
-                   graph, None, workspace, status, autotune, memo)
+                   graph, None, workspace, status, autotune, memo, gaussian)
 
 
 def sthosvd(x, ranks, oversample, prec="fp32", seed=2507, draw=0, truncate=False, rel_err=False,
-            graph=True, order=None, workspace=None, status=None, autotune=False):
-    """Randomized STHOSVD with KRPs (Algorithm 8); krp_sthosvd.  Returns (core, [Q_i], rel_err)."""
+            graph=True, order=None, workspace=None, status=None, autotune=False, gaussian=False):
+    """Randomized STHOSVD with KRPs (Algorithm 8); krp_sthosvd.  Returns (core, [Q_i], rel_err).
+
+    ``gaussian``: the dense-Gaussian RSTHOSVD baseline (KRP_FLAG_GAUSSIAN)."""
     return _tucker(_capi.lib().krp_sthosvd, x, ranks, oversample, prec, seed, draw, truncate, rel_err,
-                   graph, order, workspace, status, autotune)
+                   graph, order, workspace, status, autotune, False, gaussian)
 
 
 def range_factors(x, modes, ell, prec="fp32", seed=2507, draw=0, graph=True, memo=False, status=None):

@@ -15,7 +15,7 @@ KRP_OK, KRP_EINVAL, KRP_ENOMEM, KRP_EHIP, KRP_ECHOL, KRP_ENONFINITE, KRP_ENODEV,
 KRP_F64, KRP_F32 = 0, 1
 KRP_P_FP64, KRP_P_FP32, KRP_P_BF16, KRP_P_BF16X3 = 0, 1, 2, 3
 KRP_STAT_CHOL_SHIFT, KRP_STAT_CHOL_FAIL, KRP_STAT_NONFINITE, KRP_STAT_SINGULAR = 1, 2, 4, 8
-KRP_FLAG_NO_GRAPH, KRP_FLAG_AUTOTUNE, KRP_FLAG_MEMO = 1, 2, 4
+KRP_FLAG_NO_GRAPH, KRP_FLAG_AUTOTUNE, KRP_FLAG_MEMO, KRP_FLAG_GAUSSIAN = 1, 2, 4, 8
 
 # Every function declared in include/krp.h.
 EXPORTED = (

@@ -7,6 +7,7 @@
 #include <string>
 
 #include "../../include/krp.h"
+#include "dense.h"
 #include "kernels.h"
 
 namespace krp {
@@ -39,6 +40,8 @@ struct SketchSet {
   SketchPlan pl[kMaxDims];
   bool fused = false;  // one pass over X for all the modes
   FusedPlan fplan;
+  bool dense = false;  // KRP_FLAG_GAUSSIAN: dense Gaussian sketches instead of KRPs
+  DensePlan dp[kMaxDims];
   size_t ws_bytes = 0;
 };
 int prepare_sketches(const void* X, int dtype, int d, const int64_t* dims, int nmodes,

@@ -61,6 +61,9 @@ struct TuckerSetup {
   bool fused = false;
   FusedPlan fplan;
   size_t y_off[kMaxDims]{};
+  // KRP_FLAG_GAUSSIAN: the dense-Gaussian baselines (RHOSVD / RSTHOSVD)
+  bool dense = false;
+  DensePlan dpl[kMaxDims];
 };
 
 int plan_tucker(bool sthosvd, int dtype, int d, const int64_t* dims, const int32_t* rank,
@@ -74,6 +77,9 @@ int plan_tucker(bool sthosvd, int dtype, int d, const int64_t* dims, const int32
   if (oversample < 0) return set_error(KRP_EINVAL, "oversample must be >= 0");
   if (sthosvd && (o.flags & KRP_FLAG_MEMO))
     return set_error(KRP_EINVAL, "KRP_FLAG_MEMO applies to krp_hosvd and krp_sketch, not to krp_sthosvd");
+  s.dense = (o.flags & KRP_FLAG_GAUSSIAN) != 0;
+  if (s.dense && (o.flags & KRP_FLAG_MEMO))
+    return set_error(KRP_EINVAL, "KRP_FLAG_GAUSSIAN and KRP_FLAG_MEMO exclude each other");
   for (int k = 0; k < d; ++k) {
     s.dims[k] = dims[k];
     if (rank[k] < 1) return set_error(KRP_EINVAL, "rank[%d]=%d must be >= 1", k, rank[k]);
@@ -118,6 +124,10 @@ int plan_tucker(bool sthosvd, int dtype, int d, const int64_t* dims, const int32
     pb.sketch_id = (o.flags & KRP_FLAG_MEMO) ? kMemoSketch : (uint32_t)m;
     s.spl[step] = plan_sketch(pb, tile);
     part_max = std::max(part_max, s.spl[step].partial_bytes);
+    if (s.dense) {
+      s.dpl[step] = plan_dense(pb);
+      part_max = std::max(part_max, s.dpl[step].ws_bytes);
+    }
     part_max = std::max(part_max, cholqr_split_bytes(pb.dims[m], s.ell[m]));  // reused by the QR
     y_max = std::max(y_max, (size_t)(pb.dims[m] * s.ell[m]));
     if (sthosvd) {
@@ -131,7 +141,7 @@ int plan_tucker(bool sthosvd, int dtype, int d, const int64_t* dims, const int32
     }
   }
   s.n_sketch = d;
-  if (!sthosvd && dtype == KRP_F32) {
+  if (!sthosvd && dtype == KRP_F32 && !s.dense) {
     SketchProblem all[kMaxDims];
     for (int k = 0; k < d; ++k) all[k] = s.spb[k];
     s.fplan = plan_fused(all, d);
@@ -201,6 +211,7 @@ std::string tucker_key(const TuckerSetup& s, const krp_opts& o, const void* X, c
        "|st=" + ptr_key(status);
   for (int i = 0; i < s.n_sketch; ++i) k += "|t=" + plan_key(s.spl[i]);  // tilings (tuned or not)
   k += s.fused ? "|fused" : "";
+  k += s.dense ? "|gauss" : "";
   return k;
 }
 
@@ -243,7 +254,10 @@ int enqueue_tucker(TuckerSetup& s, const krp_opts& o, const void* X, void* core,
     SketchProblem pb = s.spb[step];
     pb.x = s.sthosvd ? cur : X;
     pb.x_is_double = s.sthosvd ? (cur64 ? 1 : 0) : (x64 ? 1 : 0);
-    if (s.fused) {
+    if (s.dense) {
+      KRP_TRY(check(launch_dense_sketch(pb, s.dpl[step], reinterpret_cast<char*>(part), y64, nullptr, 0, st),
+                    "dense sketch"));
+    } else if (s.fused) {
       y64 = reinterpret_cast<double*>(ws + s.off_y64) + s.y_off[m];
     } else {
       if (tune) {
@@ -350,7 +364,7 @@ int enqueue_tucker(TuckerSetup& s, const krp_opts& o, const void* X, void* core,
 // without the flag stay valid).  Returns true when some sketch of the sweep
 // has no entry yet.  Launches nothing.
 bool apply_cached_tiles(TuckerSetup& s, const void* X, char* ws) {
-  if (s.fused) return false;  // the fused pass has no tiling to tune
+  if (s.fused || s.dense) return false;  // the fused pass and the dense sketches have no tiling to tune
   bool missing = false;
   for (int step = 0; step < s.n_sketch; ++step) {
     SketchProblem pb = s.spb[step];
@@ -433,6 +447,10 @@ int prepare_sketches(const void* X, int dtype, int d, const int64_t* dims, int n
   SketchSet& ss = *out;
   ss.nmodes = nmodes;
   ss.out_double = dtype == KRP_F64 ? 1 : 0;
+  ss.dense = (o.flags & KRP_FLAG_GAUSSIAN) != 0;
+  if (ss.dense && (o.flags & KRP_FLAG_MEMO))
+    return set_error(KRP_EINVAL, "KRP_FLAG_GAUSSIAN and KRP_FLAG_MEMO exclude each other");
+  if (ss.dense) tune = false;
   size_t part = 0;
   for (int j = 0; j < nmodes; ++j) {
     const int m = modes[j];
@@ -457,10 +475,14 @@ int prepare_sketches(const void* X, int dtype, int d, const int64_t* dims, int n
       if (t.partial_bytes <= ss.pl[j].partial_bytes) ss.pl[j] = t;
     }
     part = std::max(part, ss.pl[j].partial_bytes);
+    if (ss.dense) {
+      ss.dp[j] = plan_dense(pb);
+      part = std::max(part, ss.dp[j].ws_bytes);
+    }
   }
   // several modes of the same tensor: one fused pass over X when it applies
   ss.fused = false;
-  if (nmodes >= 2) {
+  if (nmodes >= 2 && !ss.dense) {
     ss.fplan = plan_fused(ss.pb, nmodes);
     if (ss.fplan.ok) {
       ss.fused = true;
@@ -472,6 +494,11 @@ int prepare_sketches(const void* X, int dtype, int d, const int64_t* dims, int n
 }
 
 int enqueue_sketches(const SketchSet& ss, char* ws, void* const* Y, hipStream_t st) {
+  if (ss.dense) {
+    for (int j = 0; j < ss.nmodes; ++j)
+      KRP_TRY(check(launch_dense_sketch(ss.pb[j], ss.dp[j], ws, nullptr, Y[j], ss.out_double, st), "dense sketch"));
+    return KRP_OK;
+  }
   if (ss.fused) return check(launch_fused(ss.fplan, ss.pb, ss.nmodes, ws, nullptr, Y, ss.out_double, st), "fused sketch");
   for (int j = 0; j < ss.nmodes; ++j)
     KRP_TRY(check(launch_sketch(ss.pb[j], ss.pl[j], ws, nullptr, Y[j], ss.out_double, st), "sketch"));
@@ -506,6 +533,7 @@ int krp_sketch(const void* X, int dtype, int d, const int64_t* dims, int nmodes,
            plan_key(ss.pl[j]);
   key += ss.fused ? "|fused" : "";
   key += (o.flags & KRP_FLAG_MEMO) ? "|memo" : "";
+  key += ss.dense ? "|gauss" : "";
   return run_maybe_graph(key, !(o.flags & KRP_FLAG_NO_GRAPH), st,
                          [&](hipStream_t cs) -> int { return enqueue_sketches(ss, ws, Y, cs); });
 }
@@ -549,13 +577,18 @@ int krp_range_factors(const void* X, int dtype, int d, const int64_t* dims, int 
     key += "|" + std::to_string(modes[j]) + "," + std::to_string(ell[j]) + "," + ptr_key(Q[j]);
   key += ss.fused ? "|fused" : "";
   key += (o.flags & KRP_FLAG_MEMO) ? "|memo" : "";
+  key += ss.dense ? "|gauss" : "";
   const int out_double = dtype == KRP_F64 ? 1 : 0;
   KRP_TRY(run_maybe_graph(key, !(o.flags & KRP_FLAG_NO_GRAPH), st, [&](hipStream_t cs) -> int {
     if (!o.status_dev) KRP_TRY(check(launch_fill_int(status, 0, 1, cs), "fill"));
     double* ys[kMaxDims];
     for (int j = 0; j < nmodes; ++j) ys[j] = reinterpret_cast<double*>(ws + y_off[j]);
     void* pw = ws + part_off;
-    if (ss.fused) {
+    if (ss.dense) {
+      for (int j = 0; j < nmodes; ++j)
+        KRP_TRY(check(launch_dense_sketch(ss.pb[j], ss.dp[j], reinterpret_cast<char*>(pw), ys[j], nullptr, 0, cs),
+                      "dense sketch"));
+    } else if (ss.fused) {
       KRP_TRY(check(launch_fused(ss.fplan, ss.pb, nmodes, pw, ys, nullptr, 0, cs), "fused sketch"));
     } else {
       for (int j = 0; j < nmodes; ++j)
@@ -595,6 +628,11 @@ int krp_workspace_size(int which, int dtype, int d, const int64_t* dims, const i
   krp_opts o;
   krp_opts_default(&o);
   o.prec = prec;
+  const bool gauss = which >= 3 && which <= 5;
+  if (gauss) {
+    o.flags |= KRP_FLAG_GAUSSIAN;
+    which -= 3;
+  }
   if (which == 0) {
     size_t part = 0;
     SketchProblem all[kMaxDims];
@@ -609,13 +647,14 @@ int krp_workspace_size(int which, int dtype, int d, const int64_t* dims, const i
       pb.prec = prec;
       pb.sketch_id = (uint32_t)m;
       part = std::max(part, plan_sketch(pb, SketchTile{}).partial_bytes);
+      if (gauss) part = std::max(part, plan_dense(pb).ws_bytes);
     }
     const FusedPlan fp = plan_fused(all, d);  // the call with all modes takes the fused pass
-    if (fp.ok) part = std::max(part, fp.ws_bytes);
+    if (fp.ok && !gauss) part = std::max(part, fp.ws_bytes);
     *bytes = align_up(part);
     return KRP_OK;
   }
-  if (which != 1 && which != 2) return set_error(KRP_EINVAL, "which must be 0, 1 or 2");
+  if (which != 1 && which != 2) return set_error(KRP_EINVAL, "which must be 0..5");
   TuckerSetup s;
   KRP_TRY(plan_tucker(which == 2, dtype, d, dims, rank, oversample, o, s));
   *bytes = s.total;

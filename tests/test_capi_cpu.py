@@ -132,8 +132,24 @@ def test_workspace_size_queries(L):
         assert nb.value > 64 * 13 * 8 * 3
     assert L.krp_workspace_size(0, 1, 3, dims, _capi.i32_array((13, 13, 13)), 0, 3, ctypes.byref(nb)) == 0
     assert nb.value > 0
-    assert L.krp_workspace_size(5, 1, 3, dims, rank, 5, 1, ctypes.byref(nb)) == _capi.KRP_EINVAL
+    assert L.krp_workspace_size(6, 1, 3, dims, rank, 5, 1, ctypes.byref(nb)) == _capi.KRP_EINVAL
     assert L.krp_workspace_size(1, 0, 3, dims, rank, 5, 1, ctypes.byref(nb)) == _capi.KRP_EINVAL
+    # KRP_FLAG_GAUSSIAN (which 3..5): room for the dense Omega (64^2 x 13 for the
+    # first mode, 8 or 13 columns) and the unfolded copy of X for the later modes
+    for which in (3, 4, 5):
+        assert L.krp_workspace_size(which, 1, 3, dims, rank, 5, 1, ctypes.byref(nb)) == _capi.KRP_OK
+        assert nb.value >= 4 * (64 * 64 * 8 + 64 ** 3)
+
+
+def test_gaussian_flag_excludes_memo(L):
+    o = _capi.KrpOpts()
+    L.krp_opts_default(ctypes.byref(o))
+    o.flags = _capi.KRP_FLAG_GAUSSIAN | _capi.KRP_FLAG_MEMO
+    dims = _capi.i64_array((8, 8, 8))
+    assert L.krp_hosvd(FAKE, 1, 3, dims, _capi.i32_array((2, 2, 2)), 1, ctypes.byref(o), FAKE,
+                       _capi.ptr_array([FAKE.value] * 3), None, None) == _capi.KRP_EINVAL
+    assert L.krp_sketch(FAKE, 1, 3, dims, 1, _capi.i32_array((0,)), _capi.i32_array((4,)), ctypes.byref(o),
+                        _capi.ptr_array([FAKE.value]), None) == _capi.KRP_EINVAL
 
 
 def _hankel(L, s=(10, 12), m=8, n=8, dtype=1, r=4, ell_r=8, ell_l=12, prec=None, h=FAKE):
