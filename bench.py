@@ -23,7 +23,10 @@ ell = 17, core decay 0.8, noise 1e-4), resident in HBM before timing starts.
                  block-Hankel batch (% of the fp32 VALU peak), the sensor
                  placement of Section 6 on a 150 x 90 x 60 grid (training
                  factors, sensor selection, measurement and reconstruction of
-                 61 test fields, test error) for r = 5..30.
+                 61 test fields, test error) for r = 5..30, and the 250^4
+                 Cauchy tensor of Section 5.3 (RHOSVD-KRP, MEMO, RSTHOSVD-KRP
+                 and the dense-Gaussian RHOSVD / RSTHOSVD: time and Tucker
+                 error for r = 5..30).
 """
 from __future__ import annotations
 
@@ -366,6 +369,7 @@ def extra_workloads(stream):
         note="whole batch (sketch, QR, completion); flops of the two sketches only")
     del hd
     out["sensor_150x90x60"] = sensor_workload(stream)
+    out["cauchy_250x4"] = cauchy_workload(stream)
     return out
 
 
@@ -411,8 +415,47 @@ def sensor_workload(stream):
                      f"{out_bytes / 1e6:.0f} MB of fp32 fields")
 
 
+def cauchy_workload(stream):
+    """Section 5.3 on the 4-way Cauchy tensor (n = 250, alpha = 2; 15.6 GB in
+    fp32), equal target ranks, no oversampling: time and Tucker error of
+    RHOSVD-KRP, RHOSVD-KRP-MEMO, RSTHOSVD-KRP and the dense-Gaussian baselines
+    RHOSVD and RSTHOSVD, all with fp32 products, for r = 5..30."""
+    import torch
+    import paper_2507_23207_amd as krp
+    from synth import WORKLOADS, cauchy_tensor_torch
+
+    w = WORKLOADS["cauchy_250x4"]
+    dims = list(w["dims"])
+    x = cauchy_tensor_torch(dims, alpha=w["alpha"])
+    torch.cuda.synchronize()
+    status = torch.zeros(1, dtype=torch.int32, device="cuda")  # no host synchronisation in the timed calls
+    methods = {
+        "RHOSVD-KRP": lambda rk, **kw: krp.hosvd(x, rk, 0, prec="fp32", **kw),
+        "RHOSVD-KRP-MEMO": lambda rk, **kw: krp.hosvd(x, rk, 0, prec="fp32", memo=True, **kw),
+        "RSTHOSVD-KRP": lambda rk, **kw: krp.sthosvd(x, rk, 0, prec="fp32", **kw),
+        "RHOSVD": lambda rk, **kw: krp.hosvd(x, rk, 0, prec="fp32", gaussian=True, **kw),
+        "RSTHOSVD": lambda rk, **kw: krp.sthosvd(x, rk, 0, prec="fp32", gaussian=True, **kw),
+    }
+    rows = []
+    for r in w["ranks"]:
+        rk = [r] * len(dims)
+        row = {"r": r}
+        for name, fn in methods.items():
+            ms = gpu_ms(lambda: fn(rk, status=status), 3, stream)
+            err = fn(rk, rel_err=True)[2]
+            row[name] = {"ms": ms, "rel_err": err}
+        rows.append(row)
+        print(f"[bench] cauchy r={r} done", file=sys.stderr, flush=True)
+    del x
+    return dict(dims=dims, alpha=w["alpha"], prec="fp32", by_rank=rows,
+                note="closed-form Cauchy tensor of Section 5.3 generated on the device; each method one "
+                     "captured graph; the per-stage breakdown (RNG, unfolding, multiply, QR, core) is in "
+                     "the kernel statistics of --workload cauchy_250x4")
+
+
 # secondary workloads that can run on their own (--workload)
-SINGLE_WORKLOADS = {"sensor_150x90x60": lambda stream: sensor_workload(stream)}
+SINGLE_WORKLOADS = {"sensor_150x90x60": lambda stream: sensor_workload(stream),
+                    "cauchy_250x4": lambda stream: cauchy_workload(stream)}
 
 
 def main():
