@@ -10,6 +10,9 @@
  *   krp_hankel_lowrank  single-pass randomized SVD of block-Hankel matrices
  *                       with KRPs (Algorithm 6 with the Hankel structure of
  *                       Section 4.2), batched over instances of uneven size.
+ *   krp_kron_lowrank, krp_kron_nystrom
+ *                       Algorithm 6 and the Nystrom variant on general
+ *                       Kronecker-sum matrices (Sections 4.1, 4.3).
  *   krp_range_factors   the orthonormal factors of Algorithm 7 (sketch and
  *                       CholeskyQR) for some modes, without the core.
  *   krp_sensor_select, krp_sensor_measure, krp_sensor_reconstruct
@@ -202,6 +205,44 @@ int krp_sthosvd(const void* X, int dtype, int d, const int64_t* dims, const int3
 int krp_hankel_lowrank(int batch, const int64_t* s, int m, int n, const void* h, int dtype, int r,
                        int ell_r, int ell_l, const krp_opts* opts, void* U, void* S, void* V,
                        void* stream);
+
+/* Algorithm 6 on a general block-structured matrix written as a sum of
+ * Kronecker products, M = sum_{j<t} B_j kron C_j (Section 4.1, eq. (4.2);
+ * the 0/1 placement matrices E_j of Section 4.1 and the multilevel structures
+ * of Section 4.3, flattened into B_j, are special cases).  M is (m p) x (n q)
+ * and never formed: Y = sum_j (B_j Omega1) kr (C_j Omega2) and
+ * Z = sum_j (B_j^T Psi1) kr (C_j^T Psi2) with Omega1 (q x ell_r), Omega2
+ * (n x ell_r), Psi1 (p x ell_l), Psi2 (m x ell_l) drawn with the counters of
+ * krp_hankel_lowrank (sketch field 0, factor ids 0..3, instance 0), so a
+ * Hankel-structured input gives krp_hankel_lowrank's result.  Then Y = Q R
+ * (CholeskyQR2, shifted fallback), W = (Psi^T Q)^+ Z^T with the
+ * pseudo-inverse from the Cholesky factor of (Psi^T Q)^T (Psi^T Q), the SVD
+ * of W from the eigenvectors of W W^T, U = Q U_W.  All arithmetic fp64.
+ *   B      device, p x q x t (B_j column-major, one after the other), `dtype`
+ *   C      device, m x n x t likewise
+ *   1 <= r <= ell_r <= ell_l <= 64 (ell_l = 0: ceil(1.5 ell_r)); ell_r <=
+ *          n q; ell_l <= m p
+ *   U      device, (m p) x r; S device, r (descending); V device, (n q) x r;
+ *          row a m + b of U is row b of block row a.  Each pair is signed so
+ *          that the largest-magnitude entry of the U column is positive.
+ * Status as for krp_hankel_lowrank (KRP_ECHOL when Psi^T Q is rank-deficient
+ * or Y has no range). */
+int krp_kron_lowrank(int p, int q, int m, int n, int t, const void* B, const void* C, int dtype, int r, int ell_r,
+                     int ell_l, const krp_opts* opts, void* U, void* S, void* V, void* stream);
+
+/* The Nystrom variant (the remark after Algorithm 6) for a symmetric positive
+ * semidefinite M = sum_j B_j kron C_j (B_j p x p, C_j m x m):
+ * M ~ Y (Omega^T Y)^+ Y^T with Y = M Omega, Omega = Omega1 kr Omega2
+ * (p x ell, m x ell; factor ids 0 and 1 as above).  Computed in the shifted
+ * form: nu = sqrt(m p) 2^-52 ||Y||_F, Y_nu = Y + nu Omega,
+ * Omega^T Y_nu = R^T R, F = Y_nu R^{-1} = U Sigma V^T, Lambda =
+ * max(Sigma^2 - nu, 0); all arithmetic fp64.
+ *   U      device, (m p) x r orthonormal eigenvectors (sign as above)
+ *   Lambda device, r eigenvalues, descending; M ~ U diag(Lambda) U^T
+ *   1 <= r <= ell <= 64, ell <= m p
+ * KRP_ECHOL when Omega^T Y_nu is not positive definite (M not PSD). */
+int krp_kron_nystrom(int p, int m, int t, const void* B, const void* C, int dtype, int r, int ell,
+                     const krp_opts* opts, void* U, void* Lambda, void* stream);
 
 /* Orthonormal factors of Algorithm 7 for the listed modes only (steps 2-4:
  * KRP sketch of each mode unfolding, then CholeskyQR2 with the shifted

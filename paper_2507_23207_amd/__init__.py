@@ -21,7 +21,7 @@ PREC = {"fp64": _capi.KRP_P_FP64, "fp32": _capi.KRP_P_FP32, "bf16": _capi.KRP_P_
         "bf16x3": _capi.KRP_P_BF16X3}
 
 __all__ = ["sketch", "sketch_noalloc", "hosvd", "sthosvd", "hankel_lowrank", "gaussian", "kolda", "empty_kolda",
-           "range_factors", "sensor_select", "sensor_measure", "sensor_reconstruct",
+           "kron_lowrank", "kron_nystrom", "range_factors", "sensor_select", "sensor_measure", "sensor_reconstruct",
            "workspace_size", "hankel_workspace_size", "sensor_workspace_size", "finalize", "version", "KrpError",
            "PREC"]
 
@@ -185,6 +185,54 @@ def sthosvd(x, ranks, oversample, prec="fp32", seed=2507, draw=0, truncate=False
     ``gaussian``: the dense-Gaussian RSTHOSVD baseline (KRP_FLAG_GAUSSIAN)."""
     return _tucker(_capi.lib().krp_sthosvd, x, ranks, oversample, prec, seed, draw, truncate, rel_err,
                    graph, order, workspace, status, autotune, False, gaussian)
+
+
+def _blocks(b, c):
+    if b.dim() != 3 or c.dim() != 3 or b.shape[2] != c.shape[2]:
+        raise ValueError("B and C must be (p, q, t) and (m, n, t) stacks")
+    for x in (b, c):
+        _check_tensor(x)
+    if b.dtype != c.dtype:
+        raise ValueError("B and C need the same dtype")
+
+
+def kron_lowrank(b, c, r, ell_r, ell_l=0, seed=2507, draw=0, graph=True, status=None):
+    """Algorithm 6 on M = sum_j B_j kron C_j; krp_kron_lowrank.  ``b`` (p, q, t)
+    and ``c`` (m, n, t) with Kolda strides.  Returns (U, S, V), U (m p, r) and
+    V (n q, r) column-major."""
+    torch = _torch()
+    _blocks(b, c)
+    p, q, t = (int(v) for v in b.shape)
+    m, n, _ = (int(v) for v in c.shape)
+    u = torch.empty((r, m * p), dtype=b.dtype, device=b.device).t()
+    s = torch.empty(r, dtype=b.dtype, device=b.device)
+    v = torch.empty((r, n * q), dtype=b.dtype, device=b.device).t()
+    o, _, keep = _opts("fp64", seed, draw, graph=graph, status=status)
+    rc = _capi.lib().krp_kron_lowrank(p, q, m, n, t, ctypes.c_void_p(b.data_ptr()), ctypes.c_void_p(c.data_ptr()),
+                                      _dtype_code(b), int(r), int(ell_r), int(ell_l), ctypes.byref(o),
+                                      ctypes.c_void_p(u.data_ptr()), ctypes.c_void_p(s.data_ptr()),
+                                      ctypes.c_void_p(v.data_ptr()), _stream(b))
+    _capi.check(rc)
+    return u, s, v
+
+
+def kron_nystrom(b, c, r, ell, seed=2507, draw=0, graph=True, status=None):
+    """Nystrom approximation of the SPSD M = sum_j B_j kron C_j; krp_kron_nystrom.
+    Returns (U, Lambda) with M ~ U diag(Lambda) U^T."""
+    torch = _torch()
+    _blocks(b, c)
+    p, q, t = (int(v) for v in b.shape)
+    m, n, _ = (int(v) for v in c.shape)
+    if p != q or m != n:
+        raise ValueError("the Nystrom variant needs square blocks")
+    u = torch.empty((r, m * p), dtype=b.dtype, device=b.device).t()
+    lam = torch.empty(r, dtype=b.dtype, device=b.device)
+    o, _, keep = _opts("fp64", seed, draw, graph=graph, status=status)
+    rc = _capi.lib().krp_kron_nystrom(p, m, t, ctypes.c_void_p(b.data_ptr()), ctypes.c_void_p(c.data_ptr()),
+                                      _dtype_code(b), int(r), int(ell), ctypes.byref(o),
+                                      ctypes.c_void_p(u.data_ptr()), ctypes.c_void_p(lam.data_ptr()), _stream(b))
+    _capi.check(rc)
+    return u, lam
 
 
 def range_factors(x, modes, ell, prec="fp32", seed=2507, draw=0, graph=True, memo=False, status=None):

@@ -23,7 +23,7 @@ EXPORTED = (
     "krp_workspace_size", "krp_hankel_workspace_size", "krp_gaussian", "krp_status_string",
     "krp_last_error", "krp_version", "krp_finalize", "krp_sketch_noalloc", "krp_noalloc_scratch_bytes",
     "krp_range_factors", "krp_sensor_select", "krp_sensor_measure", "krp_sensor_reconstruct",
-    "krp_sensor_workspace_size",
+    "krp_sensor_workspace_size", "krp_kron_lowrank", "krp_kron_nystrom",
 )
 
 
@@ -76,6 +76,10 @@ def lib() -> ctypes.CDLL:
             f = getattr(L, name)
             f.argtypes = [P, i, i, I64P, I32P, i32, OP, P, ctypes.POINTER(P), I64P, P]
             f.restype = i
+        L.krp_kron_lowrank.argtypes = [i, i, i, i, i, P, P, i, i, i, i, OP, P, P, P, P]
+        L.krp_kron_lowrank.restype = i
+        L.krp_kron_nystrom.argtypes = [i, i, i, P, P, i, i, i, OP, P, P, P]
+        L.krp_kron_nystrom.restype = i
         L.krp_range_factors.argtypes = [P, i, i, I64P, i, I32P, I32P, OP, ctypes.POINTER(P), P]
         L.krp_range_factors.restype = i
         L.krp_sensor_select.argtypes = [i, I64P, I32P, i, ctypes.POINTER(P), OP, ctypes.POINTER(P),

@@ -308,3 +308,25 @@ def test_sensor_workspace_sizes(L):
     assert nb.value >= 2 * 4 * 30 * 90 * 60 * 61
     assert L.krp_sensor_workspace_size(2, 3, _capi.i64_array((150, 90, 60)), _capi.i32_array((30, 30, 30)), 61, 1,
                                        ctypes.byref(nb)) == 1
+
+
+@pytest.mark.parametrize("kw", [
+    dict(p=0), dict(t=0), dict(dtype=4), dict(r=0), dict(r=9, ell_r=8), dict(ell_r=20, ell_l=10),
+    dict(ell_l=65), dict(p=1, m=3, ell_r=4, ell_l=6), dict(B=ctypes.c_void_p(0)), dict(U=ctypes.c_void_p(0)),
+])
+def test_kron_lowrank_rejects_before_gpu(L, kw):
+    a = dict(p=5, q=4, m=3, n=6, t=2, B=FAKE, C=FAKE, dtype=0, r=3, ell_r=5, ell_l=8, U=FAKE)
+    a.update(kw)
+    rc = L.krp_kron_lowrank(a["p"], a["q"], a["m"], a["n"], a["t"], a["B"], a["C"], a["dtype"], a["r"], a["ell_r"],
+                            a["ell_l"], None, a["U"], FAKE, FAKE, None)
+    assert rc == _capi.KRP_EINVAL
+
+
+@pytest.mark.parametrize("kw", [dict(p=0), dict(r=0), dict(r=7, ell=6), dict(ell=65), dict(p=2, m=2, ell=5),
+                                dict(C=ctypes.c_void_p(0)), dict(dtype=9)])
+def test_kron_nystrom_rejects_before_gpu(L, kw):
+    a = dict(p=5, m=4, t=2, B=FAKE, C=FAKE, dtype=0, r=3, ell=6)
+    a.update(kw)
+    rc = L.krp_kron_nystrom(a["p"], a["m"], a["t"], a["B"], a["C"], a["dtype"], a["r"], a["ell"], None, FAKE, FAKE,
+                            None)
+    assert rc == _capi.KRP_EINVAL
