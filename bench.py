@@ -26,7 +26,8 @@ ell = 17, core decay 0.8, noise 1e-4), resident in HBM before timing starts.
                  61 test fields, test error) for r = 5..30, and the 250^4
                  Cauchy tensor of Section 5.3 (RHOSVD-KRP, MEMO, RSTHOSVD-KRP
                  and the dense-Gaussian RHOSVD / RSTHOSVD: time and Tucker
-                 error for r = 5..30).
+                 error for r = 5..30), and Algorithm 6 on general Kronecker
+                 sums (block-Toeplitz and block-Hankel 4096 x 4096, Nystrom).
 """
 from __future__ import annotations
 
@@ -65,6 +66,8 @@ def parse():
                     help="only run a 512 MiB copy and the headline sketch launch (for counter runs)")
     ap.add_argument("--workload", choices=sorted(SINGLE_WORKLOADS),
                     help="run one secondary workload only and print its results")
+    ap.add_argument("--methods", help="cauchy_250x4 only: comma-separated methods to run")
+    ap.add_argument("--ranks", help="cauchy_250x4 only: comma-separated target ranks")
     return ap.parse_args()
 
 
@@ -370,6 +373,7 @@ def extra_workloads(stream):
     del hd
     out["sensor_150x90x60"] = sensor_workload(stream)
     out["cauchy_250x4"] = cauchy_workload(stream)
+    out["kron_4096"] = kron_workload(stream)
     return out
 
 
@@ -436,8 +440,10 @@ def cauchy_workload(stream):
         "RHOSVD": lambda rk, **kw: krp.hosvd(x, rk, 0, prec="fp32", gaussian=True, **kw),
         "RSTHOSVD": lambda rk, **kw: krp.sthosvd(x, rk, 0, prec="fp32", gaussian=True, **kw),
     }
+    if CAUCHY_METHODS:
+        methods = {k: v for k, v in methods.items() if k in CAUCHY_METHODS}
     rows = []
-    for r in w["ranks"]:
+    for r in (CAUCHY_RANKS or w["ranks"]):
         rk = [r] * len(dims)
         row = {"r": r}
         for name, fn in methods.items():
@@ -453,9 +459,64 @@ def cauchy_workload(stream):
                      "the kernel statistics of --workload cauchy_250x4")
 
 
+def kron_workload(stream):
+    """Algorithm 6 on general Kronecker sums (Section 4.1, eq. (4.2); Section
+    4.3): a block-Toeplitz and a block-Hankel matrix of 256 x 256 blocks of
+    16 x 16 (4096 x 4096, t = 511 distinct blocks, Markov-parameter blocks
+    of a random stable system), r 12, ell 22 / 33, through krp_kron_lowrank;
+    the same Hankel instance through the specialised krp_hankel_lowrank; and
+    the Nystrom variant on an SPSD sum of 8 Kronecker products (256 x 256 and
+    16 x 16 factors)."""
+    import numpy as np
+    import torch
+    import paper_2507_23207_amd as krp
+    from synth import hankel_series, pack_hankel
+
+    s, m, r, lr, ll = 256, 16, 12, 22, 33
+    t = 2 * s - 1
+    sa, hb = hankel_series(1, s, s, m=m, n=m, n_modes=12, noise=1e-3, seed=1010)
+    h = hb[0]
+    status = torch.zeros(1, dtype=torch.int32, device="cuda")
+    c = torch.from_numpy(np.ascontiguousarray(np.transpose(h, (1, 2, 0)).transpose(2, 1, 0))).cuda()
+    c = c.permute(2, 1, 0)  # (m, n, t), Kolda strides
+    out = {}
+    for name in ("toeplitz", "hankel"):
+        # placement of block k: Toeplitz (a, a + k - (s - 1)), Hankel (a, k - a);
+        # stored (t, q, p), i.e. Kolda order of (p, q, t) after the permute
+        e = np.zeros((t, s, s))
+        for k in range(t):
+            for a in range(s):
+                bcol = k - a if name == "hankel" else a + k - (s - 1)
+                if 0 <= bcol < s:
+                    e[k, bcol, a] = 1.0
+        b = torch.from_numpy(e).cuda().permute(2, 1, 0)
+        ms = gpu_ms(lambda: krp.kron_lowrank(b, c, r, lr, ll, status=status), 5, stream)
+        out[f"kron_lowrank_{name}_ms"] = ms
+        del b
+    hd = torch.from_numpy(pack_hankel([h], np.float64)).cuda()
+    out["hankel_lowrank_same_instance_ms"] = gpu_ms(
+        lambda: krp.hankel_lowrank([s], hd, m, m, r, lr, ll, prec="fp64", status=status), 5, stream)
+    rng = np.random.default_rng(1011)
+    bs = np.stack([(lambda f: f @ f.T)(rng.standard_normal((s, 4))) * 0.8 ** j for j in range(8)], axis=2)
+    cs = np.stack([(lambda f: f @ f.T)(rng.standard_normal((m, 3))) for _ in range(8)], axis=2)
+    bd = torch.from_numpy(np.ascontiguousarray(bs.transpose(2, 1, 0))).cuda().permute(2, 1, 0)
+    cd = torch.from_numpy(np.ascontiguousarray(cs.transpose(2, 1, 0))).cuda().permute(2, 1, 0)
+    out["kron_nystrom_ms"] = gpu_ms(lambda: krp.kron_nystrom(bd, cd, r, lr, status=status), 5, stream)
+    print("[bench] kron workload done", file=sys.stderr, flush=True)
+    out.update(matrix=f"{s * m} x {s * m}", blocks=f"{s} x {s} of {m} x {m}", t=t, r=r, ell_r=lr, ell_l=ll,
+               note="fp64; the general path stores the 0/1 placement matrices densely (t s^2 entries), the "
+                    "Hankel path reads only the 2s-1 blocks")
+    return out
+
+
+# --methods / --ranks restrict the Cauchy workload (one method per profiler run)
+CAUCHY_METHODS = None
+CAUCHY_RANKS = None
+
 # secondary workloads that can run on their own (--workload)
 SINGLE_WORKLOADS = {"sensor_150x90x60": lambda stream: sensor_workload(stream),
-                    "cauchy_250x4": lambda stream: cauchy_workload(stream)}
+                    "cauchy_250x4": lambda stream: cauchy_workload(stream),
+                    "kron_4096": lambda stream: kron_workload(stream)}
 
 
 def main():
@@ -469,6 +530,9 @@ def main():
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream()
     if args.workload:
+        global CAUCHY_METHODS, CAUCHY_RANKS
+        CAUCHY_METHODS = args.methods.split(",") if args.methods else None
+        CAUCHY_RANKS = [int(v) for v in args.ranks.split(",")] if args.ranks else None
         print(json.dumps({"workload": args.workload, **SINGLE_WORKLOADS[args.workload](stream)}), flush=True)
         return
     out = headline(args, stream)

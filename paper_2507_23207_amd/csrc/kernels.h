@@ -44,7 +44,7 @@ struct SketchPlan {
   int o_fid[kMaxDims];
   int64_t o_total, o_per_wg;
   int o_ranges, f_blocks, row_blocks, col_chunks;
-  int mt, nt, wm, wo, kvec, rowvec;
+  int mt, nt, wm, wo, kvec, kvec2, rowvec;  // kvec2: 8-byte loads along f (fp32, even n_f)
   int cpad, nparts;       // nparts: one partial per workgroup (f block, o range)
   int nseg;               // level-1 segments of the reduction (1: single level)
   int lds_rows;           // factor-table rows the LDS allocation holds

@@ -193,6 +193,7 @@ SketchPlan plan_sketch(const SketchProblem& pb, const SketchTile& tile) {
   p.wo = std::max(1, wo);
   p.f_blocks = (int)((p.n_f + 31) / 32);
   p.kvec = (i != 0) && (p.n_f % vlen == 0);
+  p.kvec2 = (i != 0) && !p.kvec && !pb.x_is_double && (p.n_f % 2 == 0);
 
   int64_t o_per = tile.o_per_wg;
   if (o_per <= 0) {
@@ -267,6 +268,7 @@ hipError_t launch_sketch(const SketchProblem& pb, const SketchPlan& p, void* par
   const size_t xsz = pb.x_is_double ? 8 : 4;
   int lm = kLoadScalar;
   if ((xa & 15) == 0 && p.kvec) lm = kLoadVecF;
+  if ((xa & 7) == 0 && p.kvec2) lm = skdetail::kLoadVecF2;
   if (p.rowvec && xa % ((uintptr_t)p.mt * xsz) == 0) lm = kLoadRowVec;
   const size_t lds = p.lds_bytes;
   const dim3 grid((unsigned)(p.f_blocks * p.o_ranges), (unsigned)p.row_blocks, (unsigned)p.col_chunks);

@@ -25,11 +25,19 @@ struct SketchArgs {
 // Load modes of the X slab:
 //   kLoadScalar  one element per lane and slot (any strides);
 //   kLoadVecF    16-byte loads along the 32-wide f block (f contiguous);
+//   kLoadVecF2   the same with 2-element (8-byte) fp32 loads, for an even n_f
+//                that is not a multiple of 4;
 //   kLoadRowVec  mode 0 (rows contiguous): each lane loads MT consecutive rows
 //                of one f index as one vector and hands row MT n + m to the
 //                m-th row tile, i.e. the MT tiles of a wave interleave their
 //                rows, so the A fragments come straight from the loads.
-enum LoadMode : int { kLoadScalar = 0, kLoadVecF = 1, kLoadRowVec = 2 };
+enum LoadMode : int { kLoadScalar = 0, kLoadVecF = 1, kLoadRowVec = 2, kLoadVecF2 = 3 };
+
+// Elements per load along f of the vector modes.
+template <typename Tin, int LM>
+constexpr int vecf_width() {
+  return LM == kLoadVecF ? (int)(16 / sizeof(Tin)) : 2;
+}
 
 // Reduction slot -> k offset inside the 32-wide block.  With vector loads
 // along f (the block is contiguous in memory) lane group g reads 16-byte
@@ -37,8 +45,8 @@ enum LoadMode : int { kLoadScalar = 0, kLoadVecF = 1, kLoadRowVec = 2 };
 // instruction.
 template <typename Tin, int LM>
 __device__ __forceinline__ int kmap(int g, int j) {
-  if constexpr (LM == kLoadVecF) {
-    constexpr int V = 16 / sizeof(Tin);
+  if constexpr (LM == kLoadVecF || LM == kLoadVecF2) {
+    constexpr int V = vecf_width<Tin, LM>();
     return V * g + 4 * V * (j / V) + (j % V);
   } else {
     return 8 * g + j;
@@ -217,8 +225,8 @@ __global__ __launch_bounds__(512) void sketch_kernel(SketchArgs a) {
     for (int m = 0; m < MT; ++m) {
       const int64_t row = min(a0 + 16 * m + n, a.n_rows - 1);
       const int64_t base = off + row * a.s_row;
-      if constexpr (LM == kLoadVecF) {
-        constexpr int V = 16 / sizeof(Tin);  // n_f is a multiple of V
+      if constexpr (LM == kLoadVecF || LM == kLoadVecF2) {
+        constexpr int V = vecf_width<Tin, LM>();  // n_f is a multiple of V
 #pragma unroll
         for (int h = 0; h < 8 / V; ++h) {
           const int64_t kk = min(f0 + V * g + 4 * V * h, a.n_f - V);
@@ -410,6 +418,9 @@ template <typename Tin, int P>
 hipError_t dispatch_lm(int lm, int mt, int nt, const SketchArgs& args, dim3 grid, int threads,
                        size_t lds, hipStream_t st) {
   if (lm == kLoadVecF) return dispatch_mt<Tin, P, kLoadVecF>(mt, nt, args, grid, threads, lds, st);
+  if constexpr (sizeof(Tin) == 4) {
+    if (lm == kLoadVecF2) return dispatch_mt<Tin, P, kLoadVecF2>(mt, nt, args, grid, threads, lds, st);
+  }
   if (lm == kLoadRowVec) return dispatch_mt<Tin, P, kLoadRowVec>(mt, nt, args, grid, threads, lds, st);
   return dispatch_mt<Tin, P, kLoadScalar>(mt, nt, args, grid, threads, lds, st);
 }

@@ -35,17 +35,43 @@ struct TtmArgs {
   int p_groups;     // non-mode-0: p groups per q
 };
 
-template <typename Tin, bool KVEC>
+// Reduction slot -> k offset inside a 32-wide slice.  With vector loads of VW
+// elements along the contiguous index, lane group g reads VW-element pieces so
+// that the four groups of a row cover 4 VW contiguous elements per load.
+template <int VW>
 __device__ __forceinline__ int tkmap(int g, int j) {
-  if constexpr (KVEC) {
-    constexpr int V = 16 / sizeof(Tin);
-    return V * g + 4 * V * (j / V) + (j % V);
+  if constexpr (VW > 1) {
+    return VW * g + 4 * VW * (j / VW) + (j % VW);
   } else {
     return 8 * g + j;
   }
 }
 
-template <typename Tin, int P, bool MODE0, bool KVEC, int MT, int NT>
+// VW consecutive elements at p (aligned to VW elements).
+template <typename Tin, int VW>
+__device__ __forceinline__ void load_vec(const Tin* p, Tin (&q)[VW]) {
+  if constexpr (VW == 4) {
+    const float4 t = *reinterpret_cast<const float4*>(p);
+    q[0] = t.x;
+    q[1] = t.y;
+    q[2] = t.z;
+    q[3] = t.w;
+  } else if constexpr (VW == 2 && sizeof(Tin) == 8) {
+    const double2 t = *reinterpret_cast<const double2*>(p);
+    q[0] = t.x;
+    q[1] = t.y;
+  } else if constexpr (VW == 2) {
+    const float2 t = *reinterpret_cast<const float2*>(p);
+    q[0] = t.x;
+    q[1] = t.y;
+  } else {
+    q[0] = p[0];
+  }
+}
+
+// VW: elements per load along the reduction index of mode 0 (1, 2 or 4 for
+// fp32 storage; 1 or 2 for fp64), chosen from n and the alignment of G.
+template <typename Tin, int P, bool MODE0, int VW, int MT, int NT>
 __global__ __launch_bounds__(64 * kTtmWaves) void ttm_kernel(TtmArgs a) {
   using Pol = Policy<P>;
   using T = typename Pol::T;
@@ -104,45 +130,26 @@ __global__ __launch_bounds__(64 * kTtmWaves) void ttm_kernel(TtmArgs a) {
         for (int t = 0; t < NT; ++t) {
           T v[8];
 #pragma unroll
-          for (int j = 0; j < 8; ++j) v[j] = sl[(16 * t + n) * kSlicePitch + tkmap<Tin, KVEC>(g, j)];
+          for (int j = 0; j < 8; ++j) v[j] = sl[(16 * t + n) * kSlicePitch + tkmap<VW>(g, j)];
           bf[t] = Pol::make(v);
         }
 #pragma unroll
         for (int m = 0; m < MT; ++m) {
+          // branch-free: the row is clamped to Q - 1 and the piece to the
+          // last one (n is a multiple of VW), out-of-range values zeroed by a
+          // select after unconditional loads, so the loads stay in flight
           const int64_t qi = q0 + 16 * m + n;
           const bool qv = qi < a.Q;
-          const int64_t base = k0 + a.n * qi;
+          const int64_t base = a.n * (qv ? qi : a.Q - 1);
           T v[8];
-          if constexpr (KVEC) {
-            if constexpr (sizeof(Tin) == 4) {
 #pragma unroll
-              for (int h = 0; h < 2; ++h) {
-                const int kk = 4 * g + 16 * h;
-                float4 x = make_float4(0.f, 0.f, 0.f, 0.f);
-                if (qv && k0 + kk < a.n) x = *reinterpret_cast<const float4*>(G + base + kk);
-                v[4 * h + 0] = (T)x.x;
-                v[4 * h + 1] = (T)x.y;
-                v[4 * h + 2] = (T)x.z;
-                v[4 * h + 3] = (T)x.w;
-              }
-            } else {
+          for (int h = 0; h < 8 / VW; ++h) {
+            const int64_t kk = k0 + (VW > 1 ? VW * g + 4 * VW * h : 8 * g + h);
+            const bool kv = qv && kk < a.n;
+            Tin q[VW];
+            load_vec<Tin, VW>(G + base + (kk < a.n ? kk : a.n - VW), q);
 #pragma unroll
-              for (int h = 0; h < 4; ++h) {
-                const int kk = 2 * g + 8 * h;
-                double2 x = make_double2(0.0, 0.0);
-                if (qv && k0 + kk < a.n) x = *reinterpret_cast<const double2*>(G + base + kk);
-                v[2 * h + 0] = (T)x.x;
-                v[2 * h + 1] = (T)x.y;
-              }
-            }
-          } else {
-#pragma unroll
-            for (int j = 0; j < 8; ++j) {
-              const int kk = 8 * g + j;
-              Tin x = (Tin)0;
-              if (qv && k0 + kk < a.n) x = G[base + kk];
-              v[j] = (T)x;
-            }
+            for (int u = 0; u < VW; ++u) v[VW * h + u] = kv ? (T)q[u] : (T)0;
           }
           const typename Pol::Frag af = Pol::make(v);
 #pragma unroll
@@ -161,13 +168,13 @@ __global__ __launch_bounds__(64 * kTtmWaves) void ttm_kernel(TtmArgs a) {
         for (int t = 0; t < NT; ++t) {
           const int64_t pi = p0 + 16 * t + n;
           const bool pv = pi < a.P;
+          const int64_t pc = pv ? pi : a.P - 1;  // clamped, zeroed by the select below
           T v[8];
 #pragma unroll
           for (int j = 0; j < 8; ++j) {
             const int64_t ai = k0 + 8 * g + j;
-            Tin x = (Tin)0;
-            if (pv && ai < a.n) x = G[pi + a.P * (ai + a.n * qq)];
-            v[j] = (T)x;
+            const Tin x = G[pc + a.P * ((ai < a.n ? ai : a.n - 1) + a.n * qq)];
+            v[j] = (pv && ai < a.n) ? (T)x : (T)0;
           }
           const typename Pol::Frag bfr = Pol::make(v);
 #pragma unroll
@@ -235,7 +242,8 @@ __global__ __launch_bounds__(64 * kTtmWaves) void ttm_split_kernel(TtmArgs a) {
 #pragma unroll
       for (int j = 0; j < 8; ++j) {
         const int64_t ai = k0 + 8 * g + j;
-        x[t][j] = (pi < a.P && ai < a.n) ? G[pi + a.P * (ai + a.n * qq)] : (Tin)0;
+        const Tin y = G[(pi < a.P ? pi : a.P - 1) + a.P * ((ai < a.n ? ai : a.n - 1) + a.n * qq)];
+        x[t][j] = (pi < a.P && ai < a.n) ? y : (Tin)0;
       }
     }
   };
@@ -360,37 +368,38 @@ hipError_t ttm_split_dispatch(int tiles_c, int nt, const TtmArgs& a, hipStream_t
   }
 }
 
-template <typename Tin, int P, bool MODE0, bool KVEC, int MT, int NT>
+template <typename Tin, int P, bool MODE0, int VW, int MT, int NT>
 hipError_t ttm_go(const TtmArgs& a, hipStream_t st) {
   const unsigned grid = (unsigned)((a.items + kTtmWaves - 1) / kTtmWaves);
-  hipLaunchKernelGGL((ttm_kernel<Tin, P, MODE0, KVEC, MT, NT>), dim3(grid), dim3(64 * kTtmWaves), 0,
+  hipLaunchKernelGGL((ttm_kernel<Tin, P, MODE0, VW, MT, NT>), dim3(grid), dim3(64 * kTtmWaves), 0,
                      st, a);
   return hipGetLastError();
 }
 
+template <typename Tin, int P, int VW>
+hipError_t ttm_mode0(int tiles_c, const TtmArgs& a, hipStream_t st) {
+  switch (tiles_c) {
+    case 1: return ttm_go<Tin, P, true, VW, 4, 1>(a, st);
+    case 2: return ttm_go<Tin, P, true, VW, 4, 2>(a, st);
+    case 3: return ttm_go<Tin, P, true, VW, 4, 3>(a, st);
+    default: return ttm_go<Tin, P, true, VW, 4, 4>(a, st);
+  }
+}
+
 template <typename Tin, int P>
-hipError_t ttm_dispatch(bool mode0, bool kvec, int tiles_c, const TtmArgs& a, hipStream_t st) {
+hipError_t ttm_dispatch(bool mode0, int vw, int tiles_c, const TtmArgs& a, hipStream_t st) {
   if (mode0) {
-    if (kvec) {
-      switch (tiles_c) {
-        case 1: return ttm_go<Tin, P, true, true, 4, 1>(a, st);
-        case 2: return ttm_go<Tin, P, true, true, 4, 2>(a, st);
-        case 3: return ttm_go<Tin, P, true, true, 4, 3>(a, st);
-        default: return ttm_go<Tin, P, true, true, 4, 4>(a, st);
-      }
+    if constexpr (sizeof(Tin) == 4) {
+      if (vw == 4) return ttm_mode0<Tin, P, 4>(tiles_c, a, st);
     }
-    switch (tiles_c) {
-      case 1: return ttm_go<Tin, P, true, false, 4, 1>(a, st);
-      case 2: return ttm_go<Tin, P, true, false, 4, 2>(a, st);
-      case 3: return ttm_go<Tin, P, true, false, 4, 3>(a, st);
-      default: return ttm_go<Tin, P, true, false, 4, 4>(a, st);
-    }
+    if (vw == 2) return ttm_mode0<Tin, P, 2>(tiles_c, a, st);
+    return ttm_mode0<Tin, P, 1>(tiles_c, a, st);
   }
   switch (tiles_c) {
-    case 1: return ttm_go<Tin, P, false, false, 1, 2>(a, st);
-    case 2: return ttm_go<Tin, P, false, false, 2, 2>(a, st);
-    case 3: return ttm_go<Tin, P, false, false, 3, 2>(a, st);
-    default: return ttm_go<Tin, P, false, false, 4, 2>(a, st);
+    case 1: return ttm_go<Tin, P, false, 1, 1, 2>(a, st);
+    case 2: return ttm_go<Tin, P, false, 1, 2, 2>(a, st);
+    case 3: return ttm_go<Tin, P, false, 1, 3, 2>(a, st);
+    default: return ttm_go<Tin, P, false, 1, 4, 2>(a, st);
   }
 }
 
@@ -413,8 +422,14 @@ hipError_t launch_ttm(const TtmProblem& pb, hipStream_t st) {
   a.ldc = pb.out_ld > 0 ? pb.out_ld : pb.ell;
   const int tiles_c = (pb.ell + 15) / 16;
   const bool mode0 = (P == 1);
-  const int vec = pb.g_is_double ? 2 : 4;
-  const bool kvec = mode0 && (a.n % vec == 0) && ((reinterpret_cast<uintptr_t>(pb.g) & 15) == 0);
+  // widest aligned load along the reduction index of mode 0
+  const uintptr_t gaddr = reinterpret_cast<uintptr_t>(pb.g);
+  const size_t esz = pb.g_is_double ? 8 : 4;
+  int vw = 1;
+  if (mode0) {
+    if (!pb.g_is_double && a.n % 4 == 0 && (gaddr & 15) == 0) vw = 4;
+    else if (a.n % 2 == 0 && (gaddr & (2 * esz - 1)) == 0) vw = 2;
+  }
   // Few items (small cores): the split kernel, one workgroup per (q, group of
   // up to 64 p) with the reduction index spread over its waves.
   bool split = false;
@@ -449,13 +464,13 @@ hipError_t launch_ttm(const TtmProblem& pb, hipStream_t st) {
   }
   if (pb.g_is_double) {
     if (pb.prec != kFP64) return hipErrorInvalidValue;
-    return ttm_dispatch<double, kFP64>(mode0, kvec, tiles_c, a, st);
+    return ttm_dispatch<double, kFP64>(mode0, vw, tiles_c, a, st);
   }
   switch (pb.prec) {
-    case kFP64: return ttm_dispatch<float, kFP64>(mode0, kvec, tiles_c, a, st);
-    case kFP32: return ttm_dispatch<float, kFP32>(mode0, kvec, tiles_c, a, st);
-    case kBF16: return ttm_dispatch<float, kBF16>(mode0, kvec, tiles_c, a, st);
-    default: return ttm_dispatch<float, kBF16X3>(mode0, kvec, tiles_c, a, st);
+    case kFP64: return ttm_dispatch<float, kFP64>(mode0, vw, tiles_c, a, st);
+    case kFP32: return ttm_dispatch<float, kFP32>(mode0, vw, tiles_c, a, st);
+    case kBF16: return ttm_dispatch<float, kBF16>(mode0, vw, tiles_c, a, st);
+    default: return ttm_dispatch<float, kBF16X3>(mode0, vw, tiles_c, a, st);
   }
 }
 

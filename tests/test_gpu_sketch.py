@@ -20,6 +20,8 @@ SHAPES = [
     (200, 5, 3),         # long fast mode, tiny others
     (40, 36, 30, 24),    # outer ranges that wrap around a mode
     (24, 20, 18, 16, 10),
+    (90, 14, 6, 5),      # even first mode, not a multiple of 4: 8-byte loads along f
+    (250, 26, 9),        # the Cauchy tensor's mode size
 ]
 
 
@@ -101,3 +103,23 @@ def test_sketch_unaligned_view():
     banner("sketch unaligned")
     y = krp.sketch(xd, [1], [13], prec="fp32")[0]
     assert rel(to_host(y), _oracle_sketch(x, 1, 13)) <= 1e-5
+
+
+@pytest.mark.parametrize("dims", [(90, 14, 6, 5), (37, 11, 7), (150, 18, 12)])
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_hosvd_mode_sizes_off_the_vector_width(dims, prec):
+    """Mode-1 TTM of X with 2-element (even n_1) and scalar (odd n_1) loads
+    against the oracle's Algorithm 7."""
+    need_gpu()
+    import paper_2507_23207_amd as krp
+    from oracle.tucker import rhosvd_krp
+    from synth import low_rank_tensor
+    banner(f"hosvd dims={dims} prec={prec}")
+    ranks = [3] * len(dims)
+    x = low_rank_tensor(dims, ranks, decay=0.8, noise=1e-3, seed=41)
+    dt = torch.float64 if prec == "fp64" else torch.float32
+    xd = to_dev(x, dt)
+    core, qs, _ = krp.hosvd(xd, ranks, 2, prec=prec, seed=8)
+    g, oq = rhosvd_krp(to_host(xd), ranks, 2, seed=8)
+    tol = 1e-10 if prec == "fp64" else 2e-4
+    assert np.abs(to_host(core) - g).max() <= tol * np.abs(g).max()
