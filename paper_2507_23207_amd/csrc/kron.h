@@ -38,6 +38,14 @@ hipError_t launch_kron_scale(const double* w, const double* ev, int ell, int r, 
 // nu = sqrt_n 2^-52 sqrt(*sumsq) into *nu_out; y += nu omega (count entries).
 hipError_t launch_kron_shift(double* y, const double* omega, int64_t count, double sqrt_n, const double* sumsq,
                              double* nu_out, hipStream_t st);
+// out (la x lb, fp64 column-major) = A^T B for tall A (rows x la) and B
+// (rows x lb), la, lb <= 64: partial products over chunks of kAtbRows rows,
+// summed in a fixed order in fp64; ws holds kron_atb_bytes(rows, la, lb).
+constexpr int kAtbRows = 64;
+size_t kron_atb_bytes(int64_t rows, int la, int lb);
+hipError_t launch_kron_atb(const double* A, const double* B, int64_t rows, int la, int lb, double* out, void* ws,
+                           hipStream_t st);
+
 // Columns of u (rows x r) signed so that their largest-magnitude entry is
 // positive; v (vrows x r, may be null) takes the same signs.
 hipError_t launch_kron_sign(double* u, int64_t rows, int r, double* v, int64_t vrows, hipStream_t st);

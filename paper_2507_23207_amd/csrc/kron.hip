@@ -1,12 +1,14 @@
 // Algorithm 6 on general block-structured matrices M = sum_j B_j kron C_j
 // (Section 4.1, eq. (4.2); Section 4.3) and the Nystrom variant for SPSD M.
-// The contractions run on the TTM kernels (B_j Omega1 and C_j Omega2 for all
-// j at once, Psi^T Q, Z K^T, the small Gram matrices); this file holds what
-// is specific: the Khatri-Rao combination of the per-term products
+// The contractions with the stacked blocks and the tall-times-small products
+// run on the TTM kernels (B_j Omega1 and C_j Omega2 for all j at once, Z K^T,
+// Q U_W); this file holds what is specific: the tall A^T B products (Psi^T Q
+// and the Gram matrices) split over row chunks, the Khatri-Rao combination of the per-term products
 // (Y = sum_j (B_j Omega1) kr (C_j Omega2)), explicit KRP rows, the small
 // dense steps (pseudo-inverse by the Cholesky factor of G^T G, the Nystrom
 // Cholesky factor), the Nystrom shift, and the sign convention.
 #include "device_common.h"
+#include "driver.h"
 #include "elim.h"
 #include "kron.h"
 
@@ -189,6 +191,38 @@ __global__ __launch_bounds__(256) void kron_sign_kernel(double* __restrict__ u, 
 
 unsigned blocks_for(int64_t n) { return (unsigned)((n + 255) / 256); }
 
+// Partial A^T B over a chunk of kAtbRows rows: A (rows x la), B (rows x lb)
+// fp64 column-major; partial block z holds out[i][j] (j fastest), the layout
+// of the fixed-order reduction kernels.  The chunk of both matrices is staged
+// in LDS; each thread owns la lb / 256 outputs.
+__global__ __launch_bounds__(256) void kron_atb_kernel(const double* __restrict__ A, const double* __restrict__ B,
+                                                       int64_t rows, int la, int lb, double* __restrict__ part) {
+  __shared__ double as[kAtbRows * (kElimMaxEll + 1)];
+  __shared__ double bs[kAtbRows * (kElimMaxEll + 1)];
+  const int64_t r0 = (int64_t)blockIdx.x * kAtbRows;
+  const int nr = (int)min<int64_t>(kAtbRows, rows - r0);
+  constexpr int P = kElimMaxEll + 1;  // odd pitch: row k of the chunk at k * P
+  for (int e = threadIdx.x; e < kAtbRows * la; e += 256) {
+    const int k = e % kAtbRows, i = e / kAtbRows;
+    as[k * P + i] = k < nr ? A[r0 + k + rows * i] : 0.0;
+  }
+  for (int e = threadIdx.x; e < kAtbRows * lb; e += 256) {
+    const int k = e % kAtbRows, j = e / kAtbRows;
+    bs[k * P + j] = k < nr ? B[r0 + k + rows * j] : 0.0;
+  }
+  __syncthreads();
+  double* out = part + (int64_t)blockIdx.x * la * lb;
+  for (int e = threadIdx.x; e < la * lb; e += 256) {
+    const int i = e / lb, j = e % lb;
+    double s0 = 0.0, s1 = 0.0;
+    for (int k = 0; k < kAtbRows; k += 2) {
+      s0 += as[k * P + i] * bs[k * P + j];
+      s1 += as[(k + 1) * P + i] * bs[(k + 1) * P + j];
+    }
+    out[e] = s0 + s1;
+  }
+}
+
 }  // namespace
 
 hipError_t launch_kron_combine(const KronCombineArgs& a, hipStream_t st) {
@@ -221,6 +255,23 @@ hipError_t launch_kron_shift(double* y, const double* omega, int64_t count, doub
   hipLaunchKernelGGL(kron_shift_kernel, dim3(blocks_for(std::max<int64_t>(count, 1))), dim3(256), 0, st, y, omega,
                      count, sqrt_n, sumsq, nu_out);
   return hipGetLastError();
+}
+
+size_t kron_atb_bytes(int64_t rows, int la, int lb) {
+  const int64_t parts = (rows + kAtbRows - 1) / kAtbRows;
+  return align_up((size_t)parts * la * lb * sizeof(double)) + align_up(partial_reduce_lvl_bytes((int)parts, la, lb, 1));
+}
+
+hipError_t launch_kron_atb(const double* A, const double* B, int64_t rows, int la, int lb, double* out, void* ws,
+                           hipStream_t st) {
+  if (la < 1 || lb < 1 || la > kElimMaxEll || lb > kElimMaxEll) return hipErrorInvalidValue;
+  const int64_t parts = (rows + kAtbRows - 1) / kAtbRows;
+  double* part = reinterpret_cast<double*>(ws);
+  char* lvl = reinterpret_cast<char*>(ws) + align_up((size_t)parts * la * lb * sizeof(double));
+  hipLaunchKernelGGL(kron_atb_kernel, dim3((unsigned)parts), dim3(256), 0, st, A, B, rows, la, lb, part);
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return launch_partial_reduce(part, true, (int)parts, la, lb, lb, 1, lvl, out, nullptr, 1, st);
 }
 
 hipError_t launch_kron_sign(double* u, int64_t rows, int r, double* v, int64_t vrows, hipStream_t st) {

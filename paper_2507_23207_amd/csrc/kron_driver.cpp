@@ -5,6 +5,7 @@
 // TTMs of the stacked blocks and of the tall sketch matrices.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <string>
 
@@ -130,6 +131,7 @@ int krp_kron_lowrank(int p, int q, int m, int n, int t, const void* B, const voi
                o_d = b.take((size_t)lr * r), o_sv = b.take((size_t)r);
   const size_t o_u = b.take((size_t)rows * r), o_v = b.take((size_t)cols * r);
   const size_t o_qr = b.take(cholqr_split_bytes(rows, lr), 1);
+  const size_t o_atb = b.take(std::max(kron_atb_bytes(rows, ll, lr), kron_atb_bytes(cols, lr, lr)), 1);
   const size_t o_st = b.take(64, 1);
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   char* ws = nullptr;
@@ -162,12 +164,12 @@ int krp_kron_lowrank(int p, int q, int m, int n, int t, const void* B, const voi
     KTRY(check(launch_cholqr_split(rows, lr, D(o_y), D(o_q), nullptr, 1, ws + o_qr, status, cs), "cholqr"));
     // step 4: W = (Psi^T Q)^+ Z^T, kept as W^T = Z K^T with K = (Psi^T Q)^+
     KTRY(check(launch_kron_krp(D(o_ps1), D(o_ps2), p, m, ll, D(o_psi), cs), "Psi rows"));
-    KTRY(ttm(D(o_q), 1, rows, lr, 1, 2, 0, D(o_psi), ll, D(o_g), cs, "Psi^T Q"));
+    KTRY(check(launch_kron_atb(D(o_psi), D(o_q), rows, ll, lr, D(o_g), ws + o_atb, cs), "Psi^T Q"));
     KronSmallArgs sa{D(o_g), D(o_kt), ll, lr, kKronPinv, status};
     KTRY(check(launch_kron_small(sa, cs), "pseudo-inverse"));
     KTRY(ttm(D(o_z), 1, cols, ll, 1, 2, 1, D(o_kt), lr, D(o_wt), cs, "Z K^T"));
     // step 5: W = U_W Sigma V^T from the eigenvectors of W W^T
-    KTRY(ttm(D(o_wt), 1, cols, lr, 1, 2, 0, D(o_wt), lr, D(o_ww), cs, "W W^T"));
+    KTRY(check(launch_kron_atb(D(o_wt), D(o_wt), cols, lr, lr, D(o_ww), ws + o_atb, cs), "W W^T"));
     KTRY(check(launch_sym_eig(1, lr, r, D(o_ww), 0, D(o_uw), 0, D(o_ev), 0, cs), "eigensolver"));
     KTRY(check(launch_kron_scale(D(o_uw), D(o_ev), lr, r, nullptr, D(o_d), D(o_sv), cs), "scale"));
     // step 6: U = Q U_W, V = W^T U_W Sigma^{-1}; signs, outputs
@@ -203,6 +205,7 @@ int krp_kron_nystrom(int p, int m, int t, const void* B, const void* C, int dtyp
                o_w = b.take((size_t)ell * r), o_ev = b.take((size_t)r), o_d = b.take((size_t)ell * r),
                o_lam = b.take((size_t)r), o_u = b.take((size_t)rows * r);
   const size_t o_sum = b.take(kSumLen + 2), o_st = b.take(64, 1);
+  const size_t o_atb = b.take(kron_atb_bytes(rows, ell, ell), 1);
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   char* ws = nullptr;
   KTRY(acquire_workspace(&o, b.off, st, &ws));
@@ -227,12 +230,12 @@ int krp_kron_nystrom(int p, int m, int t, const void* B, const void* C, int dtyp
     KTRY(check(launch_kron_krp(D(o_om1), D(o_om2), p, m, ell, D(o_om), cs), "Omega rows"));
     KTRY(check(launch_sumsq(D(o_y), 1, rows * ell, sums, sums + 2, kSumLen, cs), "sumsq"));
     KTRY(check(launch_kron_shift(D(o_y), D(o_om), rows * ell, std::sqrt((double)rows), sums, sums + 1, cs), "shift"));
-    KTRY(ttm(D(o_y), 1, rows, ell, 1, 2, 0, D(o_om), ell, D(o_b), cs, "Omega^T Y"));
+    KTRY(check(launch_kron_atb(D(o_om), D(o_y), rows, ell, ell, D(o_b), ws + o_atb, cs), "Omega^T Y"));
     KronSmallArgs sa{D(o_b), D(o_ri), ell, ell, kKronCholInv, status};
     KTRY(check(launch_kron_small(sa, cs), "Cholesky"));
     KTRY(ttm(D(o_y), 1, rows, ell, 1, 2, 1, D(o_ri), ell, D(o_f), cs, "Y R^{-1}"));
     // F = U Sigma V^T: eigenvectors of F^T F; Lambda = max(Sigma^2 - nu, 0), U = F V Sigma^{-1}
-    KTRY(ttm(D(o_f), 1, rows, ell, 1, 2, 0, D(o_f), ell, D(o_ff), cs, "F^T F"));
+    KTRY(check(launch_kron_atb(D(o_f), D(o_f), rows, ell, ell, D(o_ff), ws + o_atb, cs), "F^T F"));
     KTRY(check(launch_sym_eig(1, ell, r, D(o_ff), 0, D(o_w), 0, D(o_ev), 0, cs), "eigensolver"));
     KTRY(check(launch_kron_scale(D(o_w), D(o_ev), ell, r, sums + 1, D(o_d), D(o_lam), cs), "scale"));
     KTRY(ttm(D(o_f), 1, rows, ell, 1, 2, 1, D(o_d), r, D(o_u), cs, "F V Sigma^{-1}"));
