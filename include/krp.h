@@ -82,7 +82,10 @@ enum {
   KRP_FLAG_NO_GRAPH = 1,   /* launch kernels directly instead of a cached HIP graph */
   KRP_FLAG_AUTOTUNE = 2,   /* time candidate sketch tilings on first use of a shape (dims, mode,
                               ell, precision, storage, alignment) on the call's stream and keep the
-                              fastest; results are kept per process and in the JSON file
+                              fastest; in krp_hosvd / krp_sthosvd also the tilings of the core
+                              TTMs of modes after the first (one wave per item, or the reduction
+                              split over a workgroup with 1..4 p tiles); results are kept per
+                              process and in the JSON file
                               $KRP_TUNE_CACHE (default $HOME/.cache/libkrp/sketch_tiles.json).
                               Tuned tilings never need more workspace than the default ones;
                               tuning is skipped while the stream is being captured.  The

@@ -1,4 +1,4 @@
-// Autotuner of the KRP sketch tilings (KRP_FLAG_AUTOTUNE).
+// Autotuner of the KRP sketch and TTM tilings (KRP_FLAG_AUTOTUNE).
 //
 // On the first use of a sketch shape -- (tensor dims, sketched mode, ell,
 // arithmetic, storage type, 16-byte alignment of the input) -- the candidate
@@ -11,7 +11,10 @@
 //   ...
 //   }}
 // The file is $KRP_TUNE_CACHE, else $HOME/.cache/libkrp/sketch_tiles.json.
-// Only tilings whose partial-sum buffer fits the default plan's are
+// TTM entries (keys starting "ttm ") hold {"split": s, "nt": n, "us": t}: for a
+// mode after the first, one wave per item or the split kernel with nt p tiles
+// per workgroup, timed the same way on the real input into a scratch output.
+// Only sketch tilings whose partial-sum buffer fits the default plan's are
 // considered, so workspace sizes queried without the flag remain valid.
 // Tuning never runs while the stream is being captured into a graph.
 #include <hip/hip_runtime.h>
@@ -33,7 +36,9 @@ namespace krp {
 namespace {
 
 struct Entry {
+  int kind = 0;  // 0 sketch, 1 TTM
   SketchTile tile;
+  TtmTile ttile;
   double us = 0.0;
 };
 
@@ -70,8 +75,13 @@ void load_locked() {
     const std::string key(q0 + 1, q1);
     Entry e;
     if (std::sscanf(q1 + 1, " : {\"mt\": %d, \"wm\": %d, \"wo\": %d, \"target_wgs\": %d, \"us\": %lf}",
-                    &e.tile.mt, &e.tile.wm, &e.tile.wo, &e.tile.target_wgs, &e.us) == 5)
+                    &e.tile.mt, &e.tile.wm, &e.tile.wo, &e.tile.target_wgs, &e.us) == 5) {
       g_table[key] = e;
+    } else if (std::sscanf(q1 + 1, " : {\"split\": %d, \"nt\": %d, \"us\": %lf}", &e.ttile.split, &e.ttile.nt,
+                           &e.us) == 3) {
+      e.kind = 1;
+      g_table[key] = e;
+    }
   }
   std::fclose(f);
 }
@@ -87,9 +97,13 @@ void save_locked() {
   size_t i = 0;
   for (const auto& kv : g_table) {
     const Entry& e = kv.second;
-    std::fprintf(f, "\"%s\": {\"mt\": %d, \"wm\": %d, \"wo\": %d, \"target_wgs\": %d, \"us\": %.3f}%s\n",
-                 kv.first.c_str(), e.tile.mt, e.tile.wm, e.tile.wo, e.tile.target_wgs, e.us,
-                 ++i < g_table.size() ? "," : "");
+    const char* sep = ++i < g_table.size() ? "," : "";
+    if (e.kind == 1)
+      std::fprintf(f, "\"%s\": {\"split\": %d, \"nt\": %d, \"us\": %.3f}%s\n", kv.first.c_str(), e.ttile.split,
+                   e.ttile.nt, e.us, sep);
+    else
+      std::fprintf(f, "\"%s\": {\"mt\": %d, \"wm\": %d, \"wo\": %d, \"target_wgs\": %d, \"us\": %.3f}%s\n",
+                   kv.first.c_str(), e.tile.mt, e.tile.wm, e.tile.wo, e.tile.target_wgs, e.us, sep);
   }
   std::fprintf(f, "}}\n");
   std::fclose(f);
@@ -105,6 +119,15 @@ std::string tune_key(const SketchProblem& pb) {
   return k;
 }
 
+std::string ttm_key(const TtmProblem& pb) {
+  std::string k = "ttm d=" + std::to_string(pb.d) + " dims=";
+  for (int i = 0; i < pb.d; ++i) k += (i ? "x" : "") + std::to_string(pb.dims[i]);
+  k += " mode=" + std::to_string(pb.mode) + " ell=" + std::to_string(pb.ell) + " prec=" + std::to_string(pb.prec) +
+       " gd=" + std::to_string(pb.g_is_double) + " ld=" + std::to_string(pb.out_ld) +
+       " al=" + std::to_string((reinterpret_cast<uintptr_t>(pb.g) & 15) == 0 ? 1 : 0);
+  return k;
+}
+
 bool same_geometry(const SketchPlan& a, const SketchPlan& b) {
   return a.mt == b.mt && a.wm == b.wm && a.wo == b.wo && a.o_per_wg == b.o_per_wg &&
          a.row_blocks == b.row_blocks && a.f_blocks == b.f_blocks;
@@ -116,9 +139,79 @@ bool cached_tile(const SketchProblem& pb, SketchTile* out) {
   std::lock_guard<std::mutex> lk(g_tune_mu);
   load_locked();
   auto it = g_table.find(tune_key(pb));
-  if (it == g_table.end()) return false;
+  if (it == g_table.end() || it->second.kind != 0) return false;
   *out = it->second.tile;
   return true;
+}
+
+bool cached_ttm_tile(const TtmProblem& pb, TtmTile* out) {
+  TtmTile c[8];
+  if (ttm_tile_candidates(pb, c, 8) < 2) {  // a single tiling: nothing to tune
+    *out = TtmTile{};
+    return true;
+  }
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  load_locked();
+  auto it = g_table.find(ttm_key(pb));
+  if (it == g_table.end() || it->second.kind != 1) return false;
+  *out = it->second.ttile;
+  return true;
+}
+
+TtmTile tuned_ttm_tile(const TtmProblem& pb, hipStream_t st) {
+  const TtmTile def{};
+  if (!pb.g || !pb.q64) return def;
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(st, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return def;
+  TtmTile hit;
+  if (cached_ttm_tile(pb, &hit)) return hit;
+  TtmTile cands[8];
+  const int nc = ttm_tile_candidates(pb, cands, 8);
+  int64_t out_elems = pb.out_ld > 0 ? pb.out_ld : pb.ell;
+  for (int k = 0; k < pb.d; ++k)
+    if (k != pb.mode) out_elems *= pb.dims[k];
+  void* out = nullptr;
+  constexpr int kReps = 11;
+  hipEvent_t ev[kReps + 1] = {};
+  bool ok = hipMalloc(&out, std::max<size_t>((size_t)out_elems * (pb.out_is_double ? 8 : 4), 256)) == hipSuccess;
+  for (int i = 0; ok && i <= kReps; ++i) ok = hipEventCreate(&ev[i]) == hipSuccess;
+  std::vector<double> med(nc, -1.0);
+  for (int i = 0; ok && i < nc; ++i) {
+    TtmProblem t = pb;
+    t.out = out;
+    t.tile = cands[i];
+    for (int w = 0; ok && w < 2; ++w) ok = launch_ttm(t, st) == hipSuccess;
+    ok = ok && hipEventRecord(ev[0], st) == hipSuccess;
+    for (int r = 0; ok && r < kReps; ++r)
+      ok = launch_ttm(t, st) == hipSuccess && hipEventRecord(ev[r + 1], st) == hipSuccess;
+    ok = ok && hipEventSynchronize(ev[kReps]) == hipSuccess;
+    std::vector<double> tm;
+    for (int r = 0; ok && r < kReps; ++r) {
+      float ms = 0.f;
+      ok = hipEventElapsedTime(&ms, ev[r], ev[r + 1]) == hipSuccess;
+      tm.push_back(ms * 1000.0);
+    }
+    if (ok) {
+      std::sort(tm.begin(), tm.end());
+      med[i] = tm[kReps / 2];
+    }
+  }
+  for (int i = 0; i <= kReps; ++i)
+    if (ev[i]) hipEventDestroy(ev[i]);
+  if (out) hipFree(out);
+  (void)hipGetLastError();
+  if (!ok || med[0] < 0.0) return def;
+  int best = 0;
+  for (int i = 1; i < nc; ++i)
+    if (med[i] > 0.0 && med[i] < 0.98 * med[0] && med[i] < med[best]) best = i;
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  Entry e;
+  e.kind = 1;
+  e.ttile = cands[best];
+  e.us = med[best];
+  g_table[ttm_key(pb)] = e;
+  save_locked();
+  return cands[best];
 }
 
 SketchTile tuned_tile(const SketchProblem& pb, hipStream_t st) {
@@ -189,7 +282,10 @@ SketchTile tuned_tile(const SketchProblem& pb, hipStream_t st) {
   for (size_t i = 1; i < cands.size(); ++i)
     if (med[i] > 0.0 && med[i] < 0.98 * med[0] && med[i] < med[best]) best = i;
   std::lock_guard<std::mutex> lk(g_tune_mu);
-  g_table[key] = Entry{cands[best].first, med[best]};
+  Entry e;
+  e.tile = cands[best].first;
+  e.us = med[best];
+  g_table[key] = e;
   save_locked();
   return cands[best].first;
 }

@@ -129,6 +129,15 @@ hipError_t launch_cholqr_split(int64_t n, int ell, const double* y64, double* q6
 // out_ld > ell the output mode has extent out_ld and these ell columns are a
 // chunk of it: `out` then points at the chunk's first column (element offset
 // c0 for mode 0, c0 * prod(dims before mode) otherwise).
+// Tiling of a TTM of a mode after the first (the autotuner's choice):
+// split < 0 keeps the planner's choice, 0 one wave per item, 1 the split
+// kernel (the reduction spread over the waves of a workgroup) with nt p tiles
+// per workgroup (0: the planner's).  Mode 1 has a single tiling.
+struct TtmTile {
+  int split = -1;
+  int nt = 0;
+};
+
 struct TtmProblem {
   const void* g = nullptr;
   int g_is_double = 0;
@@ -141,8 +150,16 @@ struct TtmProblem {
   int prec = 0;
   const double* q64 = nullptr;
   int64_t out_ld = 0;  // 0: ell
+  TtmTile tile;
 };
 hipError_t launch_ttm(const TtmProblem& pb, hipStream_t st);
+// Candidate tilings of a TTM problem (the default first); mode 1 has one.
+int ttm_tile_candidates(const TtmProblem& pb, TtmTile* out, int max);
+// The fastest TTM tiling of this shape (tuning table, else timed now on
+// pb.g / pb.q64 into a scratch output, median of repeated launches, kept only
+// when faster than the default by a margin); never while `st` is capturing.
+TtmTile tuned_ttm_tile(const TtmProblem& pb, hipStream_t st);
+bool cached_ttm_tile(const TtmProblem& pb, TtmTile* out);
 
 // Casts between storage types (count elements).
 hipError_t launch_cast(const void* in, int in_is_double, void* out, int out_is_double,

@@ -434,13 +434,15 @@ hipError_t launch_ttm(const TtmProblem& pb, hipStream_t st) {
   // up to 64 p) with the reduction index spread over its waves.
   bool split = false;
   int split_nt = 4;
+  const int nt_max = pb.prec == kFP64 ? (tiles_c >= 4 ? 1 : 2) : (tiles_c >= 4 ? 3 : 4);
+  const bool want_split = pb.tile.split >= 0 ? pb.tile.split == 1 : Q * ((P + 31) / 32) < kSplitMaxWaves;
   if (mode0) {
     a.items = (Q + 63) / 64;
     a.p_groups = 1;
-  } else if (Q * ((P + 31) / 32) < kSplitMaxWaves) {
+  } else if (want_split) {
     split = true;
-    const int nt_max = pb.prec == kFP64 ? (tiles_c >= 4 ? 1 : 2) : (tiles_c >= 4 ? 3 : 4);
-    split_nt = (int)std::min<int64_t>(nt_max, (P + 15) / 16);
+    const int nt = pb.tile.nt > 0 ? std::min(pb.tile.nt, nt_max) : nt_max;
+    split_nt = (int)std::min<int64_t>(nt, (P + 15) / 16);
     a.p_groups = (int)((P + 16 * split_nt - 1) / (16 * split_nt));
     a.items = Q * a.p_groups;
   } else {
@@ -474,5 +476,20 @@ hipError_t launch_ttm(const TtmProblem& pb, hipStream_t st) {
   }
 }
 
+
+int ttm_tile_candidates(const TtmProblem& pb, TtmTile* out, int max) {
+  int n = 0;
+  if (max < 1) return 0;
+  out[n++] = TtmTile{};  // the planner's choice
+  int64_t P = 1;
+  for (int k = 0; k < pb.mode; ++k) P *= pb.dims[k];
+  if (P == 1) return n;  // mode 1: one tiling
+  const int tiles_c = (pb.ell + 15) / 16;
+  const int nt_max = pb.prec == kFP64 ? (tiles_c >= 4 ? 1 : 2) : (tiles_c >= 4 ? 3 : 4);
+  if (n < max) out[n++] = TtmTile{0, 0};
+  for (int nt = 1; nt <= nt_max && n < max; ++nt)
+    if (16 * (nt - 1) < P) out[n++] = TtmTile{1, nt};
+  return n;
+}
 
 }  // namespace krp

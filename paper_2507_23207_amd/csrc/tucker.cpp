@@ -64,7 +64,26 @@ struct TuckerSetup {
   // KRP_FLAG_GAUSSIAN: the dense-Gaussian baselines (RHOSVD / RSTHOSVD)
   bool dense = false;
   DensePlan dpl[kMaxDims];
+  // tilings of the core TTMs (KRP_FLAG_AUTOTUNE; default otherwise)
+  TtmTile ttile[kMaxDims];
 };
+
+// The TTM of step `step` of the core chain (mode order of the sweep) on g.
+TtmProblem core_ttm(const TuckerSetup& s, int step, const void* g, bool g64, const double* q64, void* out) {
+  TtmProblem tp;
+  tp.g = g;
+  tp.g_is_double = g64 ? 1 : 0;
+  tp.d = s.d;
+  for (int k = 0; k < s.d; ++k) tp.dims[k] = s.ttm_in_dims[step][k];
+  tp.mode = s.ttm_mode[step];
+  tp.ell = s.ell[tp.mode];
+  tp.prec = s.prec;
+  tp.q64 = q64;
+  tp.out = out;
+  tp.out_is_double = s.out64 ? 1 : 0;
+  tp.tile = s.ttile[step];
+  return tp;
+}
 
 int plan_tucker(bool sthosvd, int dtype, int d, const int64_t* dims, const int32_t* rank,
                 int32_t oversample, const krp_opts& o, TuckerSetup& s) {
@@ -272,17 +291,8 @@ int enqueue_tucker(TuckerSetup& s, const krp_opts& o, const void* X, void* core,
                                       part, status, st),
                   "cholqr"));
     if (s.sthosvd) {
-      TtmProblem tp;
-      tp.g = cur;
-      tp.g_is_double = cur64 ? 1 : 0;
-      tp.d = d;
-      for (int k = 0; k < d; ++k) tp.dims[k] = s.ttm_in_dims[step][k];
-      tp.mode = m;
-      tp.ell = s.ell[m];
-      tp.prec = s.prec;
-      tp.q64 = q64;
-      tp.out = cores[step & 1];
-      tp.out_is_double = s.out64 ? 1 : 0;
+      TtmProblem tp = core_ttm(s, step, cur, cur64, q64, cores[step & 1]);
+      if (tune) tp.tile = s.ttile[step] = tuned_ttm_tile(tp, st);
       KRP_TRY(check(launch_ttm(tp, st), "ttm"));
       cur = tp.out;
       cur64 = s.out64;
@@ -292,17 +302,9 @@ int enqueue_tucker(TuckerSetup& s, const krp_opts& o, const void* X, void* core,
     cur = X;
     cur64 = x64;
     for (int step = 0; step < d; ++step) {
-      TtmProblem tp;
-      tp.g = cur;
-      tp.g_is_double = cur64 ? 1 : 0;
-      tp.d = d;
-      for (int k = 0; k < d; ++k) tp.dims[k] = s.ttm_in_dims[step][k];
-      tp.mode = step;
-      tp.ell = s.ell[step];
-      tp.prec = s.prec;
-      tp.q64 = reinterpret_cast<double*>(ws + s.off_q64[step]);
-      tp.out = cores[step & 1];
-      tp.out_is_double = s.out64 ? 1 : 0;
+      TtmProblem tp = core_ttm(s, step, cur, cur64, reinterpret_cast<double*>(ws + s.off_q64[step]),
+                               cores[step & 1]);
+      if (tune) tp.tile = s.ttile[step] = tuned_ttm_tile(tp, st);
       KRP_TRY(check(launch_ttm(tp, st), "ttm"));
       cur = tp.out;
       cur64 = s.out64;
@@ -381,6 +383,29 @@ bool apply_cached_tiles(TuckerSetup& s, const void* X, char* ws) {
   return missing;
 }
 
+// The same for the core TTMs: cached tilings go into s.ttile; true when some
+// TTM of the chain has no entry yet.  Launches nothing.
+bool apply_cached_ttm_tiles(TuckerSetup& s, const void* X, char* ws) {
+  bool missing = false;
+  bool g64 = s.dtype == KRP_F64;
+  for (int step = 0; step < s.d; ++step) {
+    const void* g = step == 0 ? X : static_cast<const void*>(ws + s.off_core[(step - 1) & 1]);
+    TtmProblem tp = core_ttm(s, step, g, step == 0 ? g64 : s.out64, nullptr, ws + s.off_core[step & 1]);
+    TtmTile t;
+    if (cached_ttm_tile(tp, &t))
+      s.ttile[step] = t;
+    else
+      missing = true;
+  }
+  return missing;
+}
+
+std::string ttm_tiles_key(const TuckerSetup& s) {
+  std::string k = "|ttm=";
+  for (int step = 0; step < s.d; ++step) k += std::to_string(s.ttile[step].split) + "." + std::to_string(s.ttile[step].nt) + ",";
+  return k;
+}
+
 bool stream_capturing(hipStream_t st) {
   hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
   return hipStreamIsCapturing(st, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone;
@@ -414,11 +439,15 @@ int tucker_entry(bool sthosvd, const void* X, int dtype, int d, const int64_t* d
   // input.  Nothing is tuned, allocated or synchronised while the caller's
   // stream is being captured.
   bool tune_now = false;
-  if (o.flags & KRP_FLAG_AUTOTUNE) tune_now = apply_cached_tiles(s, X, ws) && !stream_capturing(st);
+  if (o.flags & KRP_FLAG_AUTOTUNE) {
+    const bool sk_missing = apply_cached_tiles(s, X, ws);
+    const bool ttm_missing = !s.dense && apply_cached_ttm_tiles(s, X, ws);
+    tune_now = (sk_missing || ttm_missing) && !stream_capturing(st);
+  }
   if (tune_now) {
     KRP_TRY(enqueue_tucker(s, o, X, core, Q, ws, status, want_err, true, st));
   } else {
-    const std::string key = tucker_key(s, o, X, core, Q, ws, status, want_err);
+    const std::string key = tucker_key(s, o, X, core, Q, ws, status, want_err) + ttm_tiles_key(s);
     KRP_TRY(run_maybe_graph(key, !(o.flags & KRP_FLAG_NO_GRAPH), st, [&](hipStream_t cs) {
       return enqueue_tucker(s, o, X, core, Q, ws, status, want_err, false, cs);
     }));

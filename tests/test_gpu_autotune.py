@@ -61,3 +61,30 @@ def test_autotuned_sthosvd_matches_oracle(tmp_path, monkeypatch):
     e_gpu = ot.tucker_rel_error(x, to_host(core), [to_host(q) for q in qs])
     assert abs(e_gpu - e_ref) <= 0.01 * e_ref, (e_gpu, e_ref)
     assert abs(err - e_ref) <= 0.01 * e_ref, (err, e_ref)
+
+
+def test_autotuned_ttm_tilings(tmp_path, monkeypatch):
+    """Core TTMs of the STHOSVD chain tuned too: TTM entries in the cache for
+    every mode after the first, the tuned call within rounding of the
+    untuned one, and the cached call (captured graph) equal to the tuned."""
+    need_gpu()
+    import paper_2507_23207_amd as krp
+    cache = tmp_path / "tiles.json"
+    monkeypatch.setenv("KRP_TUNE_CACHE", str(cache))
+    x = low_rank_tensor((48, 40, 36, 30), (6, 6, 6, 6), decay=0.85, noise=1e-3, seed=33)
+    xd = to_dev(x, torch.float32)
+    banner("autotune ttm tilings")
+    c0, q0, _ = krp.sthosvd(xd, [6] * 4, 3, prec="fp32")
+    c1, q1, _ = krp.sthosvd(xd, [6] * 4, 3, prec="fp32", autotune=True)   # tunes (direct launches)
+    c2, q2, _ = krp.sthosvd(xd, [6] * 4, 3, prec="fp32", autotune=True)   # cached tilings, graph
+    torch.cuda.synchronize()
+    data = json.loads(cache.read_text())["entries"]
+    # the table is process-wide: this sweep's TTMs are the 4-way ones
+    tk = [k for k in data if k.startswith("ttm d=4 ") and k.split()[2].endswith("x30")]
+    assert len(tk) == 3, data  # modes 2..4 (mode 1 has a single tiling)
+    for k in tk:
+        assert data[k]["split"] in (-1, 0, 1) and data[k]["us"] > 0
+    assert rel(to_host(c1), to_host(c0)) <= 1e-5
+    assert torch.equal(c1, c2)
+    for a, b in zip(q1, q2):
+        assert torch.equal(a, b)
