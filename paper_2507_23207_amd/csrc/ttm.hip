@@ -168,13 +168,13 @@ __global__ __launch_bounds__(64 * kTtmWaves) void ttm_kernel(TtmArgs a) {
         for (int t = 0; t < NT; ++t) {
           const int64_t pi = p0 + 16 * t + n;
           const bool pv = pi < a.P;
-          const int64_t pc = pv ? pi : a.P - 1;  // clamped, zeroed by the select below
           T v[8];
 #pragma unroll
           for (int j = 0; j < 8; ++j) {
             const int64_t ai = k0 + 8 * g + j;
-            const Tin x = G[pc + a.P * ((ai < a.n ? ai : a.n - 1) + a.n * qq)];
-            v[j] = (pv && ai < a.n) ? (T)x : (T)0;
+            Tin x = (Tin)0;
+            if (pv && ai < a.n) x = G[pi + a.P * (ai + a.n * qq)];
+            v[j] = (T)x;
           }
           const typename Pol::Frag bfr = Pol::make(v);
 #pragma unroll
@@ -242,8 +242,7 @@ __global__ __launch_bounds__(64 * kTtmWaves) void ttm_split_kernel(TtmArgs a) {
 #pragma unroll
       for (int j = 0; j < 8; ++j) {
         const int64_t ai = k0 + 8 * g + j;
-        const Tin y = G[(pi < a.P ? pi : a.P - 1) + a.P * ((ai < a.n ? ai : a.n - 1) + a.n * qq)];
-        x[t][j] = (pi < a.P && ai < a.n) ? y : (Tin)0;
+        x[t][j] = (pi < a.P && ai < a.n) ? G[pi + a.P * (ai + a.n * qq)] : (Tin)0;
       }
     }
   };
