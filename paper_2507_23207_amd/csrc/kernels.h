@@ -151,6 +151,9 @@ struct TtmProblem {
   const double* q64 = nullptr;
   int64_t out_ld = 0;  // 0: ell
   TtmTile tile;
+  // mode 1 only: write zeros to the output columns ell..out_ld-1 (a padded
+  // extent of the compressed mode)
+  bool zero_pad = false;
 };
 hipError_t launch_ttm(const TtmProblem& pb, hipStream_t st);
 // Candidate tilings of a TTM problem (the default first); mode 1 has one.
@@ -167,6 +170,10 @@ hipError_t launch_cast(const void* in, int in_is_double, void* out, int out_is_d
 // Sum of squares of a storage-type array into *acc (fp64, cleared first).
 hipError_t launch_sumsq(const void* x, int is_double, int64_t count, double* acc,
                         double* scratch, int scratch_len, hipStream_t st);
+// dst (rows x cols, leading dimension rows) = the first rows rows of src
+// (leading dimension src_ld): removes the padding of a tensor's first mode.
+hipError_t launch_compact_rows(const void* src, int64_t src_ld, void* dst, int64_t rows, int64_t cols, int is_double,
+                               hipStream_t st);
 // Fills count ints with value (graph-safe replacement for memset).
 hipError_t launch_fill_int(int* p, int value, int64_t count, hipStream_t st);
 

@@ -31,6 +31,7 @@ struct TtmArgs {
   int64_t P, n, Q;  // g[p, a, q] sizes
   int ell;
   int64_t ldc;      // extent of the output mode (ell, or more for a column chunk)
+  int cw;           // output columns written: ell, or ldc when the padding is zero-filled
   int64_t items;
   int p_groups;     // non-mode-0: p groups per q
 };
@@ -196,7 +197,7 @@ __global__ __launch_bounds__(64 * kTtmWaves) void ttm_kernel(TtmArgs a) {
         if constexpr (MODE0) {
           const int64_t qi = q0 + 16 * m + Pol::out_row(g, r);
           const int c = 16 * t + n;
-          if (qi < a.Q && c < a.ell) out[c + a.ldc * qi] = (Tout)acc[m][t][r];
+          if (qi < a.Q && c < a.cw) out[c + a.ldc * qi] = (Tout)acc[m][t][r];
         } else {
           const int c = 16 * m + Pol::out_row(g, r);
           const int64_t pi = p0 + 16 * t + n;
@@ -419,7 +420,9 @@ hipError_t launch_ttm(const TtmProblem& pb, hipStream_t st) {
   a.Q = Q;
   a.ell = pb.ell;
   a.ldc = pb.out_ld > 0 ? pb.out_ld : pb.ell;
-  const int tiles_c = (pb.ell + 15) / 16;
+  a.cw = pb.zero_pad ? (int)a.ldc : pb.ell;  // the accumulators of columns past ell are zero
+  if (pb.zero_pad && (P != 1 || a.ldc > 64)) return hipErrorInvalidValue;
+  const int tiles_c = (a.cw + 15) / 16;
   const bool mode0 = (P == 1);
   // widest aligned load along the reduction index of mode 0
   const uintptr_t gaddr = reinterpret_cast<uintptr_t>(pb.g);

@@ -66,6 +66,12 @@ struct TuckerSetup {
   DensePlan dpl[kMaxDims];
   // tilings of the core TTMs (KRP_FLAG_AUTOTUNE; default otherwise)
   TtmTile ttile[kMaxDims];
+  // STHOSVD: extent the TTM of each step gives its mode (ell, or for mode 1
+  // ell padded with zero rows to the vector width of the core's type, so that
+  // the later sketches, whose contiguous index it is, load whole vectors);
+  // pad0 is the final extent of mode 1 (the core is compacted at the end)
+  int64_t ttm_ext[kMaxDims]{};
+  int64_t pad0 = 0;
 };
 
 // The TTM of step `step` of the core chain (mode order of the sweep) on g.
@@ -82,6 +88,10 @@ TtmProblem core_ttm(const TuckerSetup& s, int step, const void* g, bool g64, con
   tp.out = out;
   tp.out_is_double = s.out64 ? 1 : 0;
   tp.tile = s.ttile[step];
+  if (s.sthosvd && s.ttm_ext[step] > tp.ell) {
+    tp.out_ld = s.ttm_ext[step];
+    tp.zero_pad = true;
+  }
   return tp;
 }
 
@@ -152,7 +162,15 @@ int plan_tucker(bool sthosvd, int dtype, int d, const int64_t* dims, const int32
     if (sthosvd) {
       s.ttm_mode[step] = m;
       for (int k = 0; k < d; ++k) s.ttm_in_dims[step][k] = cur[k];
-      cur[m] = s.ell[m];
+      // mode 1, compressed before the last step, is padded with zero rows to the
+      // vector width (the extra factor rows of later sketches multiply zeros);
+      // not for the dense baselines, whose Omega rows follow the core's indexing
+      const int64_t vlen = s.out64 ? 2 : 4;
+      int64_t ext = s.ell[m];
+      if (m == 0 && !s.dense && step + 1 < d) ext = (ext + vlen - 1) / vlen * vlen;
+      s.ttm_ext[step] = ext;
+      if (m == 0) s.pad0 = ext;
+      cur[m] = ext;
       int64_t e = 1;
       for (int k = 0; k < d; ++k) e *= cur[k];
       s.ttm_out_elems[step] = e;
@@ -310,7 +328,14 @@ int enqueue_tucker(TuckerSetup& s, const krp_opts& o, const void* X, void* core,
       cur64 = s.out64;
     }
   }
-  // `cur` holds the ell-sized core in the compute type.
+  // `cur` holds the ell-sized core in the compute type (STHOSVD: mode 1 padded).
+  if (s.sthosvd && s.pad0 > s.ell[0]) {
+    int64_t rest = 1;
+    for (int k = 1; k < d; ++k) rest *= s.ell[k];
+    void* dst = (cur == cores[0]) ? cores[1] : cores[0];
+    KRP_TRY(check(launch_compact_rows(cur, s.pad0, dst, s.ell[0], rest, cur64 ? 1 : 0, st), "compact core"));
+    cur = dst;
+  }
   if (trunc) {
     double* qs[kMaxDims];
     for (int k = 0; k < d; ++k) qs[k] = reinterpret_cast<double*>(ws + s.off_q64[k]);

@@ -65,6 +65,29 @@ unsigned grid_for(int64_t n, int t) {
 
 }  // namespace
 
+template <typename T>
+__global__ void compact_rows_kernel(const T* __restrict__ src, int64_t src_ld, T* __restrict__ dst, int64_t rows,
+                                    int64_t n) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n) return;
+  const int64_t c = e / rows, r = e - c * rows;
+  dst[e] = src[r + src_ld * c];
+}
+
+hipError_t launch_compact_rows(const void* src, int64_t src_ld, void* dst, int64_t rows, int64_t cols, int is_double,
+                               hipStream_t st) {
+  const int64_t n = rows * cols;
+  if (n == 0) return hipSuccess;
+  const unsigned grid = (unsigned)((n + 255) / 256);
+  if (is_double)
+    hipLaunchKernelGGL(compact_rows_kernel<double>, dim3(grid), dim3(256), 0, st,
+                       reinterpret_cast<const double*>(src), src_ld, reinterpret_cast<double*>(dst), rows, n);
+  else
+    hipLaunchKernelGGL(compact_rows_kernel<float>, dim3(grid), dim3(256), 0, st,
+                       reinterpret_cast<const float*>(src), src_ld, reinterpret_cast<float*>(dst), rows, n);
+  return hipGetLastError();
+}
+
 hipError_t launch_cast(const void* in, int in_is_double, void* out, int out_is_double, int64_t count,
                        hipStream_t st) {
   if (count == 0) return hipSuccess;
