@@ -113,11 +113,14 @@ __device__ __forceinline__ double rsqrt_nr(double x) {
   y = y * fma(-hx * y, y, 1.5);
   return y;
 }
-__device__ __forceinline__ double rcp_nr(double x) {
-  double y = __builtin_amdgcn_rcp(x);
-  y = fma(y, fma(-x, y, 1.0), y);
-  y = fma(y, fma(-x, y, 1.0), y);
-  return y;
+// One Newton step each, for quantities that need not be exact.
+__device__ __forceinline__ double rsqrt_nr1(double x) {
+  const double y = __builtin_amdgcn_rsq(x);
+  return y * fma(-0.5 * x * y, y, 1.5);
+}
+__device__ __forceinline__ double rcp_nr1(double x) {
+  const double y = __builtin_amdgcn_rcp(x);
+  return fma(y, fma(-x, y, 1.0), y);
 }
 
 __device__ __forceinline__ int jacobi_sigma(int x, int half) {
@@ -255,10 +258,10 @@ __global__ __launch_bounds__(kEigThreads) void jacobi_eig_kernel(int ell, int r,
       if (lane < half) {
         // rotation of positions (2k, 2k+1) zeroing their off-diagonal entry:
         // t = tan(phi) = sign(d) 2 apq / (|d| + sqrt(d^2 + 4 apq^2)), d = aqq - app
-        // The reciprocal square roots and the reciprocal use the hardware
-        // estimates refined by two Newton steps each: t only has to be close
-        // to the exact angle (c and s stay exactly normalised by c = 1 /
-        // sqrt(1 + t^2), s = t c), and this keeps the dependent chain short.
+        // t only has to be close to the exact angle (c and s stay exactly
+        // normalised by c = 1 / sqrt(1 + t^2), s = t c): its reciprocal
+        // square root and reciprocal take the hardware estimates and one
+        // Newton step each, c's two, which keeps the dependent chain short.
         const int p = 2 * lane;
         const double app = Ac[p * P + p], apq = Ac[p * P + p + 1], aqq = Ac[(p + 1) * P + p + 1];
         const double d = aqq - app;
@@ -266,8 +269,8 @@ __global__ __launch_bounds__(kEigThreads) void jacobi_eig_kernel(int ell, int r,
         const double num = 2.0 * apq;
         const double x = fma(d, d, num * num);
         if (apq != 0.0 && x >= 0x1.0p-1000) {  // (entries below ~1e-150 count as zero)
-          const double hyp = x * rsqrt_nr(x);
-          t = num * rcp_nr(fabs(d) + hyp);
+          const double hyp = x * rsqrt_nr1(x);
+          t = num * rcp_nr1(fabs(d) + hyp);
           if (d < 0.0) t = -t;
         }
         const double c = rsqrt_nr(fma(t, t, 1.0));
