@@ -15,7 +15,8 @@ struct TruncPlan {
   int d = 0;
   int ell[kMaxDims]{}, rank[kMaxDims]{}, order[kMaxDims]{};
   int64_t dims[kMaxDims]{};
-  size_t off_g[2]{}, off_gram[kMaxDims]{}, off_v0[kMaxDims]{}, off_w[kMaxDims]{}, off_qt[kMaxDims]{};
+  size_t off_g[2]{}, off_gram[kMaxDims]{}, off_part[kMaxDims]{}, off_v0[kMaxDims]{}, off_w[kMaxDims]{},
+      off_qt[kMaxDims]{};
   size_t ws_bytes = 0;
 };
 

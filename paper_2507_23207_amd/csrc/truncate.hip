@@ -15,13 +15,13 @@ namespace krp {
 namespace {
 
 constexpr int kEigThreads = 512;
-constexpr int kGramThreads = 256;
 constexpr int kEigMax = 64;
 
-// Gram matrix of mode `mode` of a fp64 tensor viewed as [P][l][Q]:
-// gram[a + l b] = sum_{p,q} g[p, a, q] g[p, b, q].  One block per pair a <= b.
-// Entry pair (a <= b) of the Gram matrix of the mode unfolding of g viewed as
-// g[p, a, q] (P x l x Q): sum over p, q of g[p, a, q] g[p, b, q].
+// Small tensors (one mode): one workgroup per entry pair a <= b of the Gram
+// matrix, summing g[p, a, q] g[p, b, q] over p, q (more workgroups than the
+// column split would have, each with few loads).
+constexpr int kGramThreads = 256;
+constexpr int64_t kGramPairMaxElems = 1 << 18;
 __device__ void mode_gram_pair(const double* __restrict__ g, int64_t P, int l, int64_t Q,
                                double* __restrict__ gram, int pair, double* red) {
   int b = 0;
@@ -63,21 +63,228 @@ __global__ void mode_gram_kernel(const double* __restrict__ g, int64_t P, int l,
   mode_gram_pair(g, P, l, Q, gram, blockIdx.x, red);
 }
 
-// The Gram matrices of several mode unfoldings of one tensor in one launch:
-// workgroups [first[m], first[m + 1]) take the entry pairs of mode m.
+// Gram matrices of mode unfoldings of a fp64 tensor viewed as g[p, a, q]
+// (P x l x Q): gram[a + l b] = sum over the columns k = p + P q of
+// g[p, a, q] g[p, b, q].  The columns of each mode are split into nparts
+// contiguous ranges, one workgroup each: it streams its range in chunks of
+// kGramCh columns through LDS (column-major in k: xs[k][a]) and accumulates
+// the 16 x 16 tiles of the upper triangle on the fp64 matrix cores, each
+// tile's chunk split over several waves when there are few tiles; the tile
+// accumulators are summed in wave order and the workgroup's partial Gram
+// matrix (both triangles) goes to part[w][l][l].  A second kernel adds the
+// partials of each entry in workgroup order.  Every sum has a fixed order.
+constexpr int kGramCh = 64;
+constexpr int kGramPitch = kEigMax + 1;
+constexpr int kGramWgThreads = 512;
+constexpr int kGramMaxParts = 256;
+
 struct GramJobs {
   int64_t P[kMaxDims], Q[kMaxDims];
   int l[kMaxDims];
-  double* gram[kMaxDims];
-  int first[kMaxDims + 1];
+  double* part[kMaxDims];  // nparts x l x l partial Gram matrices
+  double* gram[kMaxDims];  // l x l result
+  int nparts[kMaxDims];
+  int first[kMaxDims + 1];  // workgroups [first[m], first[m + 1]) take mode m
   int n;
 };
 
-__global__ void mode_gram_multi_kernel(const double* __restrict__ g, GramJobs jobs) {
-  __shared__ double red[kGramThreads / 64];
+// Column ranges per mode: one chunk per workgroup up to kGramMaxParts
+// workgroups (small cores: every chunk at once), and at most 2^19 partial
+// entries.
+int gram_parts(int64_t K, int l) {
+  int64_t np = (K + kGramCh - 1) / kGramCh;
+  np = std::min<int64_t>(np, kGramMaxParts);
+  np = std::min<int64_t>(np, std::max<int64_t>(1, (int64_t)(1 << 19) / ((int64_t)l * l)));
+  return (int)std::max<int64_t>(1, np);
+}
+
+__global__ __launch_bounds__(kGramWgThreads) void gram_part_kernel(const double* __restrict__ g, GramJobs jobs) {
+  __shared__ double xs[kGramCh * kGramPitch];
   int m = 0;
   while (m + 1 < jobs.n && (int)blockIdx.x >= jobs.first[m + 1]) ++m;
-  mode_gram_pair(g, jobs.P[m], jobs.l[m], jobs.Q[m], jobs.gram[m], (int)blockIdx.x - jobs.first[m], red);
+  const int w = (int)blockIdx.x - jobs.first[m];
+  const int64_t P = jobs.P[m], Q = jobs.Q[m];
+  const int l = jobs.l[m], np = jobs.nparts[m];
+  const int64_t K = P * Q;
+  const int64_t kb = K * w / np, ke = K * (w + 1) / np;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int nl = lane & 15, gq = lane >> 4;
+  const int T = (l + 15) / 16, lp = 16 * T;
+  const int pairs = T * (T + 1) / 2;
+  // tasks: tile pairs x splits of the chunk's 16 column quads over the waves
+  const int ks = pairs == 1 ? 8 : pairs <= 2 ? 4 : pairs <= 4 ? 2 : 1;
+  const int tasks = pairs * ks, qper = 16 / ks;
+  int ti[2] = {0, 0}, tj[2] = {0, 0};
+#pragma unroll
+  for (int u = 0; u < 2; ++u) {
+    const int pr = (wave + u * 8) % pairs;
+    int cnt = 0;
+    for (int a = 0; a < T; ++a)
+      for (int b = a; b < T; ++b) {
+        if (cnt == pr) {
+          ti[u] = a;
+          tj[u] = b;
+        }
+        ++cnt;
+      }
+  }
+  doublex4 acc[2] = {doublex4{0.0, 0.0, 0.0, 0.0}, doublex4{0.0, 0.0, 0.0, 0.0}};
+  // chunk loads, coalesced along the contiguous index: a for mode 0 (P = 1),
+  // the column k (p fastest) otherwise; zeros past the range and past l.  The
+  // next chunk's loads are in flight while the current one is multiplied.
+  constexpr int kPer = kGramCh * kEigMax / kGramWgThreads;
+  double pre[kPer];
+  auto slot = [&](int e, int& kk, int& a) {
+    if (P == 1) {
+      kk = e / lp;
+      a = e - kk * lp;
+    } else {
+      a = e >> 6;  // kGramCh = 64 columns per a
+      kk = e & 63;
+    }
+  };
+  // column k0 of the chunk as (q0, p0), advanced chunk by chunk (uniform);
+  // within the chunk column k0 + kk is (q0 + x / P, x % P), x = p0 + kk < P + 64
+  int64_t q0 = P == 1 ? kb : kb / P;
+  int64_t p0 = P == 1 ? 0 : kb - q0 * P;
+  const float rcp_p = 1.0f / (float)min(P, (int64_t)64);
+  auto load = [&](int64_t k0) {
+    const int kc = (int)min((int64_t)kGramCh, ke - k0);
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+      const int e = tid + u * kGramWgThreads;
+      int kk, a;
+      slot(e, kk, a);
+      double v = 0.0;
+      if (e < kGramCh * lp && kk < kc && a < l) {
+        int64_t off;
+        if (P == 1) {
+          off = a + (int64_t)l * (k0 + kk);
+        } else {
+          const int64_t x = p0 + kk;
+          int64_t qd, pr;
+          if (P >= 64) {
+            qd = x >= P ? 1 : 0;
+          } else {  // x < 128: the float quotient is exact or one off
+            qd = (int64_t)((float)x * rcp_p);
+            if (qd * P > x) --qd;
+            else if ((qd + 1) * P <= x) ++qd;
+          }
+          pr = x - qd * P;
+          off = pr + P * (a + (int64_t)l * (q0 + qd));
+        }
+        v = g[off];
+      }
+      pre[u] = v;
+    }
+  };
+  auto advance = [&]() {
+    if (P == 1) return;
+    p0 += kGramCh;
+    while (p0 >= P) {
+      p0 -= P;
+      ++q0;
+    }
+  };
+  if (kb < ke) load(kb);
+  for (int64_t k0 = kb; k0 < ke; k0 += kGramCh) {
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+      const int e = tid + u * kGramWgThreads;
+      int kk, a;
+      slot(e, kk, a);
+      if (e < kGramCh * lp) xs[kk * kGramPitch + a] = pre[u];
+    }
+    __syncthreads();
+    advance();
+    if (k0 + kGramCh < ke) load(k0 + kGramCh);
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int task = wave + u * 8;
+      if (task < tasks) {
+        const int kh = task / pairs;
+        double av[4], bv[4];
+#pragma unroll 1
+        for (int s0 = 0; s0 < qper; s0 += 4) {
+#pragma unroll
+          for (int s = 0; s < 4; ++s) {
+            const int kk = 4 * (kh * qper + min(s0 + s, qper - 1)) + gq;
+            av[s] = xs[kk * kGramPitch + 16 * ti[u] + nl];
+            bv[s] = xs[kk * kGramPitch + 16 * tj[u] + nl];
+          }
+#pragma unroll
+          for (int s = 0; s < 4; ++s)
+            if (s0 + s < qper) acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[s], bv[s], acc[u], 0, 0, 0);
+        }
+      }
+    }
+    __syncthreads();
+  }
+  // tile accumulators of each task into LDS, then the splits of a tile pair
+  // in order (16 tasks x 256 entries fit the chunk buffer)
+#pragma unroll
+  for (int u = 0; u < 2; ++u) {
+    const int task = wave + u * 8;
+    if (task < tasks) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) xs[task * 256 + (4 * r + gq) * 16 + nl] = acc[u][r];
+    }
+  }
+  __syncthreads();
+  double* out = jobs.part[m] + (int64_t)w * l * l;
+  for (int e = tid; e < pairs * 256; e += kGramWgThreads) {
+    const int pr = e / 256, i = (e % 256) / 16, j = e % 16;
+    int a0 = 0, b0 = 0, cnt = 0;
+    for (int a = 0; a < T; ++a)
+      for (int b = a; b < T; ++b) {
+        if (cnt == pr) {
+          a0 = a;
+          b0 = b;
+        }
+        ++cnt;
+      }
+    double v = 0.0;
+    for (int kh = 0; kh < ks; ++kh) v += xs[(pr + pairs * kh) * 256 + i * 16 + j];
+    const int ga = 16 * a0 + i, gb = 16 * b0 + j;
+    if (ga < l && gb < l) {
+      out[ga + (int64_t)l * gb] = v;
+      out[gb + (int64_t)l * ga] = v;
+    }
+  }
+}
+
+// gram[e] = sum of the partials' entry e in workgroup order: a workgroup owns
+// 16 entries of one mode (blockIdx.y), its 16 thread groups sum consecutive
+// sixteenths of the partials, and those are added in order.
+__global__ __launch_bounds__(256) void gram_sum_kernel(GramJobs jobs) {
+  __shared__ double red[256];
+  const int m = blockIdx.y;
+  const int l = jobs.l[m], np = jobs.nparts[m];
+  const int64_t E = (int64_t)l * l;
+  const int el = threadIdx.x & 15, grp = threadIdx.x >> 4;
+  const int64_t e = (int64_t)blockIdx.x * 16 + el;
+  const int per = (np + 15) / 16, q0 = grp * per, q1 = min(np, q0 + per);
+  double s = 0.0;
+  if (e < E) {
+    const double* src = jobs.part[m] + e;
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    int q = q0;
+    for (; q + 3 < q1; q += 4) {
+      s0 += src[(int64_t)q * E];
+      s1 += src[(int64_t)(q + 1) * E];
+      s2 += src[(int64_t)(q + 2) * E];
+      s3 += src[(int64_t)(q + 3) * E];
+    }
+    for (; q < q1; ++q) s0 += src[(int64_t)q * E];
+    s = (s0 + s1) + (s2 + s3);
+  }
+  red[threadIdx.x] = s;
+  __syncthreads();
+  if (grp == 0 && e < E) {
+    double t = 0.0;
+    for (int k = 0; k < 16; ++k) t += red[16 * k + el];
+    jobs.gram[m][e] = t;
+  }
 }
 
 __device__ __forceinline__ void wave_sync() {
@@ -401,6 +608,10 @@ TruncPlan plan_truncate(int d, const int* ell, const int* rank, const int64_t* d
   p.off_g[0] = take(elems * sizeof(double));
   p.off_g[1] = take(elems * sizeof(double));
   for (int k = 0; k < d; ++k) p.off_gram[k] = take((size_t)ell[k] * ell[k] * sizeof(double));
+  // partial Gram matrices: the ell-core has the most columns per mode, so its
+  // partition also bounds those of the partially truncated cores
+  for (int k = 0; k < d; ++k)
+    p.off_part[k] = take((size_t)gram_parts(elems / ell[k], ell[k]) * ell[k] * ell[k] * sizeof(double));
   for (int k = 0; k < d; ++k) p.off_v0[k] = take((size_t)ell[k] * ell[k] * sizeof(double));
   for (int k = 0; k < d; ++k) p.off_w[k] = take((size_t)ell[k] * rank[k] * sizeof(double));
   for (int k = 0; k < d; ++k) p.off_qt[k] = take((size_t)dims[k] * rank[k] * sizeof(double));
@@ -448,13 +659,32 @@ hipError_t launch_truncate(const TruncPlan& p, const void* core, int core_double
   double* g[2] = {reinterpret_cast<double*>(ws + p.off_g[0]), reinterpret_cast<double*>(ws + p.off_g[1])};
   hipError_t e = launch_cast(core, core_double, g[0], 1, elems, st);
   if (e != hipSuccess) return e;
-  auto gram_of = [&](const double* src, int i, double* gram) {
-    int64_t P = 1, Q = 1;
-    for (int k = 0; k < i; ++k) P *= cur[k];
-    for (int k = i + 1; k < d; ++k) Q *= cur[k];
-    const int l = (int)cur[i];
-    hipLaunchKernelGGL(mode_gram_kernel, dim3(l * (l + 1) / 2), dim3(kGramThreads), 0, st, src, P, l, Q,
-                       gram);
+  // Gram matrices of the modes `modes` of the tensor src (sizes cur)
+  auto grams_of = [&](const double* src, int nm, const int* modes) -> hipError_t {
+    GramJobs gj{};
+    gj.n = nm;
+    gj.first[0] = 0;
+    int lmax = 1;
+    for (int j = 0; j < nm; ++j) {
+      const int i = modes[j];
+      int64_t P = 1, Q = 1;
+      for (int k = 0; k < i; ++k) P *= cur[k];
+      for (int k = i + 1; k < d; ++k) Q *= cur[k];
+      const int l = (int)cur[i];
+      gj.P[j] = P;
+      gj.Q[j] = Q;
+      gj.l[j] = l;
+      gj.nparts[j] = gram_parts(P * Q, l);
+      gj.part[j] = reinterpret_cast<double*>(ws + p.off_part[i]);
+      gj.gram[j] = reinterpret_cast<double*>(ws + p.off_gram[i]);
+      gj.first[j + 1] = gj.first[j] + gj.nparts[j];
+      lmax = std::max(lmax, l);
+    }
+    hipLaunchKernelGGL(gram_part_kernel, dim3(gj.first[nm]), dim3(kGramWgThreads), 0, st, src, gj);
+    hipError_t err = hipGetLastError();
+    if (err != hipSuccess) return err;
+    hipLaunchKernelGGL(gram_sum_kernel, dim3((unsigned)((lmax * lmax + 15) / 16), (unsigned)nm), dim3(256), 0, st,
+                       gj);
     return hipGetLastError();
   };
   // The Gram matrices of all modes of the ell-core, and their complete
@@ -464,24 +694,13 @@ hipError_t launch_truncate(const TruncPlan& p, const void* core, int core_double
   // only by the discarded components, so its Jacobi iteration starts from
   // that basis and needs few sweeps.
   EigJob jobs[kMaxDims];
-  GramJobs gj{};
-  gj.n = d;
-  gj.first[0] = 0;
+  int all[kMaxDims];
   for (int i = 0; i < d; ++i) {
-    double* gram = reinterpret_cast<double*>(ws + p.off_gram[i]);
-    int64_t P = 1, Q = 1;
-    for (int k = 0; k < i; ++k) P *= cur[k];
-    for (int k = i + 1; k < d; ++k) Q *= cur[k];
-    const int l = (int)cur[i];
-    gj.P[i] = P;
-    gj.Q[i] = Q;
-    gj.l[i] = l;
-    gj.gram[i] = gram;
-    gj.first[i + 1] = gj.first[i] + l * (l + 1) / 2;
-    jobs[i] = EigJob{gram, nullptr, reinterpret_cast<double*>(ws + p.off_v0[i]), nullptr, p.ell[i], p.ell[i]};
+    all[i] = i;
+    jobs[i] = EigJob{reinterpret_cast<double*>(ws + p.off_gram[i]), nullptr,
+                     reinterpret_cast<double*>(ws + p.off_v0[i]), nullptr, p.ell[i], p.ell[i]};
   }
-  hipLaunchKernelGGL(mode_gram_multi_kernel, dim3(gj.first[d]), dim3(kGramThreads), 0, st, g[0], gj);
-  e = hipGetLastError();
+  e = grams_of(g[0], d, all);
   if (e != hipSuccess) return e;
   e = launch_sym_eig_jobs(d, jobs, st);
   if (e != hipSuccess) return e;
@@ -495,7 +714,16 @@ hipError_t launch_truncate(const TruncPlan& p, const void* core, int core_double
       e = launch_cast(v0, 1, wi, 1, (int64_t)l * p.rank[i], st);
     } else {
       double* gram = reinterpret_cast<double*>(ws + p.off_gram[i]);
-      e = gram_of(g[s & 1], i, gram);
+      int64_t P = 1, Q = 1;
+      for (int k = 0; k < i; ++k) P *= cur[k];
+      for (int k = i + 1; k < d; ++k) Q *= cur[k];
+      if (P * Q * l <= kGramPairMaxElems) {
+        hipLaunchKernelGGL(mode_gram_kernel, dim3(l * (l + 1) / 2), dim3(kGramThreads), 0, st, g[s & 1], P, l,
+                           Q, gram);
+        e = hipGetLastError();
+      } else {
+        e = grams_of(g[s & 1], 1, &i);
+      }
       if (e != hipSuccess) return e;
       e = launch_sym_eig(1, l, p.rank[i], gram, 0, wi, 0, nullptr, 0, st, v0, 0);
     }

@@ -6,8 +6,11 @@
 // Mode 0 (p empty): MFMA tile D[q][c] = sum_a G[a, q] Q[a, c]; the reduction
 // runs along the contiguous index a (vector loads), results are written row
 // by row of the l x (rest) output.
-// Other modes: D[c][p] = sum_a Q[a, c] g[p, a, q]; 16 consecutive p form the
-// coalesced B operand and the output columns.
+// Other modes: D[c][(p, q)] = sum_a Q[a, c] g[p, a, q]; 16 columns (p, q)
+// form the B operand and the output columns: 16 consecutive p of one q, or,
+// for a short p range (a compressed first mode, P < 64), 16 consecutive
+// values of the flattened index J = p + P q (runs of P contiguous elements,
+// a tile may span several q), which leaves no lanes idle.
 // The workgroup walks the reduction index in 32-wide slices in lockstep; each
 // slice of Q is staged once in LDS (double-buffered) for all its waves.
 #include "device_common.h"
@@ -23,6 +26,7 @@ namespace {
 constexpr int kTtmWaves = 8;
 constexpr int kSlicePitch = 36;  // 32 reduction slots + padding (elements)
 constexpr int64_t kSplitMaxWaves = 8192;  // below this many one-wave items, the split kernel
+constexpr int kTtmColTiles = 2;  // non-mode-0: 16-column tiles of (p, q) per wave
 
 struct TtmArgs {
   const void* g;
@@ -33,7 +37,7 @@ struct TtmArgs {
   int64_t ldc;      // extent of the output mode (ell, or more for a column chunk)
   int cw;           // output columns written: ell, or ldc when the padding is zero-filled
   int64_t items;
-  int p_groups;     // non-mode-0: p groups per q
+  int p_groups;     // non-mode-0: p groups per q (0: flattened (p, q) columns)
 };
 
 // Reduction slot -> k offset inside a 32-wide slice.  With vector loads of VW
@@ -85,12 +89,30 @@ __global__ __launch_bounds__(64 * kTtmWaves) void ttm_kernel(TtmArgs a) {
   const int n = lane & 15, g = lane >> 4;
   const int64_t item = (int64_t)blockIdx.x * kTtmWaves + wave;
   const bool active = item < a.items;
-  int64_t q0 = 0, p0 = 0, qq = 0;
+  int64_t q0 = 0;
+  // non-mode-0: element (p, a = 0, q) of the tile-t column J = 16 (NT item + t) + n
+  int64_t jb[NT], jo[NT];
+  bool jv[NT];
   if constexpr (MODE0) {
     q0 = item * (16 * MT);
-  } else {
-    qq = item / a.p_groups;
-    p0 = (item % a.p_groups) * (16 * NT);
+  } else if (a.p_groups == 0) {  // flattened (p, q) columns
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      const int64_t J = (item * NT + t) * 16 + n;
+      jv[t] = J < a.P * a.Q;
+      const int64_t qi = J / a.P, pi = J - qi * a.P;
+      jb[t] = pi + a.P * a.n * qi;
+      jo[t] = pi + a.P * a.ldc * qi;
+    }
+  } else {  // groups of 16 NT consecutive p of one q
+    const int64_t qi = item / a.p_groups;
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      const int64_t pi = (item % a.p_groups) * (16 * NT) + 16 * t + n;
+      jv[t] = pi < a.P;
+      jb[t] = pi + a.P * a.n * qi;
+      jo[t] = pi + a.P * a.ldc * qi;
+    }
   }
   const Tin* G = reinterpret_cast<const Tin*>(a.g);
 
@@ -167,14 +189,12 @@ __global__ __launch_bounds__(64 * kTtmWaves) void ttm_kernel(TtmArgs a) {
         }
 #pragma unroll
         for (int t = 0; t < NT; ++t) {
-          const int64_t pi = p0 + 16 * t + n;
-          const bool pv = pi < a.P;
           T v[8];
 #pragma unroll
           for (int j = 0; j < 8; ++j) {
             const int64_t ai = k0 + 8 * g + j;
             Tin x = (Tin)0;
-            if (pv && ai < a.n) x = G[pi + a.P * (ai + a.n * qq)];
+            if (jv[t] && ai < a.n) x = G[jb[t] + a.P * ai];
             v[j] = (T)x;
           }
           const typename Pol::Frag bfr = Pol::make(v);
@@ -200,8 +220,7 @@ __global__ __launch_bounds__(64 * kTtmWaves) void ttm_kernel(TtmArgs a) {
           if (qi < a.Q && c < a.cw) out[c + a.ldc * qi] = (Tout)acc[m][t][r];
         } else {
           const int c = 16 * m + Pol::out_row(g, r);
-          const int64_t pi = p0 + 16 * t + n;
-          if (pi < a.P && c < a.ell) out[pi + a.P * (c + a.ldc * qq)] = (Tout)acc[m][t][r];
+          if (jv[t] && c < a.ell) out[jo[t] + a.P * c] = (Tout)acc[m][t][r];
         }
       }
 }
@@ -396,10 +415,10 @@ hipError_t ttm_dispatch(bool mode0, int vw, int tiles_c, const TtmArgs& a, hipSt
     return ttm_mode0<Tin, P, 1>(tiles_c, a, st);
   }
   switch (tiles_c) {
-    case 1: return ttm_go<Tin, P, false, 1, 1, 2>(a, st);
-    case 2: return ttm_go<Tin, P, false, 1, 2, 2>(a, st);
-    case 3: return ttm_go<Tin, P, false, 1, 3, 2>(a, st);
-    default: return ttm_go<Tin, P, false, 1, 4, 2>(a, st);
+    case 1: return ttm_go<Tin, P, false, 1, 1, kTtmColTiles>(a, st);
+    case 2: return ttm_go<Tin, P, false, 1, 2, kTtmColTiles>(a, st);
+    case 3: return ttm_go<Tin, P, false, 1, 3, kTtmColTiles>(a, st);
+    default: return ttm_go<Tin, P, false, 1, 4, kTtmColTiles>(a, st);
   }
 }
 
@@ -448,8 +467,14 @@ hipError_t launch_ttm(const TtmProblem& pb, hipStream_t st) {
     a.p_groups = (int)((P + 16 * split_nt - 1) / (16 * split_nt));
     a.items = Q * a.p_groups;
   } else {
-    a.p_groups = (int)((P + 31) / 32);
-    a.items = Q * a.p_groups;
+    constexpr int cw = 16 * kTtmColTiles;  // (p, q) columns of a wave
+    if (P < 64) {
+      a.p_groups = 0;
+      a.items = (P * Q + cw - 1) / cw;
+    } else {
+      a.p_groups = (int)((P + cw - 1) / cw);
+      a.items = Q * a.p_groups;
+    }
   }
   if (a.items == 0) return hipSuccess;
   const bool wants_double_out = pb.prec == kFP64;
