@@ -354,7 +354,22 @@ def extra_workloads(stream):
         hosvd_ms=hos, memo_all_modes_ms=allm_memo,
         memo_all_modes_gbps_vs_one_read=(xb + 4 * 128 * ell * 4) / allm_memo / 1e6, memo_hosvd_ms=hos_memo)
     del x
-    # 256-instance block-Hankel batch
+    out["hankel_256_fp32"] = hankel_workload(stream)
+    out["sensor_150x90x60"] = sensor_workload(stream)
+    out["cauchy_250x4"] = cauchy_workload(stream)
+    out["kron_4096"] = kron_workload(stream)
+    return out
+
+
+def hankel_workload(stream):
+    """The 256-instance block-Hankel batch (Algorithm 6 on the Section 4.2
+    workload shape): whole-batch time and the sketches' rate against the FP32
+    VALU peak."""
+    import numpy as np
+    import torch
+    import paper_2507_23207_amd as krp
+    from synth import WORKLOADS, hankel_series, pack_hankel
+
     w = WORKLOADS["hankel_256_fp32"]
     s, blocks = hankel_series(w["batch"], w["s_lo"], w["s_hi"], m=w["m"], n=w["n"],
                               n_modes=w["n_modes"], noise=w["noise"], seed=w["seed"])
@@ -366,15 +381,12 @@ def extra_workloads(stream):
     # (2 (2s - 1) m n ell_r); Z likewise with n, ell_l
     flops = sum(2.0 * sb * sb * (m * w["ell_r"] + n * w["ell_l"])
                 + 2.0 * (2 * sb - 1) * m * n * (w["ell_r"] + w["ell_l"]) for sb in s)
-    out["hankel_256_fp32"] = dict(
+    res = dict(
         ms=hms, sketch_gflop=flops / 1e9, tflops=flops / hms / 1e9,
         frac_fp32_valu_peak=flops / hms / 1e9 / FP32_VALU_PEAK_TFLOPS,
         note="whole batch (sketch, QR, completion); flops of the two sketches only")
     del hd
-    out["sensor_150x90x60"] = sensor_workload(stream)
-    out["cauchy_250x4"] = cauchy_workload(stream)
-    out["kron_4096"] = kron_workload(stream)
-    return out
+    return res
 
 
 def sensor_workload(stream):
@@ -514,7 +526,8 @@ CAUCHY_METHODS = None
 CAUCHY_RANKS = None
 
 # secondary workloads that can run on their own (--workload)
-SINGLE_WORKLOADS = {"sensor_150x90x60": lambda stream: sensor_workload(stream),
+SINGLE_WORKLOADS = {"hankel_256_fp32": lambda stream: hankel_workload(stream),
+                    "sensor_150x90x60": lambda stream: sensor_workload(stream),
                     "cauchy_250x4": lambda stream: cauchy_workload(stream),
                     "kron_4096": lambda stream: kron_workload(stream)}
 
