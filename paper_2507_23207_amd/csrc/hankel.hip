@@ -922,10 +922,13 @@ struct FinArgs {
 // aligned): 16 table entries read at a time, four partial sums.  The argmax
 // and the write pass use the same function, so a value is computed the same
 // way in both.
-__device__ __forceinline__ double dot_row(const double (&x)[kHankelMaxEll], const double* b) {
+// NB: 16-entry blocks that hold the row's ell entries (the blocks past them
+// are zero in x and b and are not visited).
+template <int NB>
+__device__ __forceinline__ double dot_row(const double (&x)[16 * NB], const double* b) {
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-  for (int k0 = 0; k0 < kHankelMaxEll; k0 += 16) {
+  for (int k0 = 0; k0 < 16 * NB; k0 += 16) {
     double bl[16];
 #pragma unroll
     for (int u = 0; u < 16; u += 2) {
@@ -939,7 +942,7 @@ __device__ __forceinline__ double dot_row(const double (&x)[kHankelMaxEll], cons
   return (acc[0] + acc[1]) + (acc[2] + acc[3]);
 }
 
-template <typename T>
+template <typename T, int NBU>
 __global__ __launch_bounds__(kChThreads) void hankel_argmax_kernel(FinArgs a) {
   __shared__ __align__(16) double bu[kHankelMaxEll * kHankelMaxEll];
   __shared__ double rv[kChThreads / 64][kHankelMaxEll];
@@ -959,15 +962,15 @@ __global__ __launch_bounds__(kChThreads) void hankel_argmax_kernel(FinArgs a) {
   }
   __syncthreads();
   const T* Y = reinterpret_cast<const T*>(a.y) + a.t.y_off[b];
-  double yv[kHankelMaxEll];
+  double yv[16 * NBU];
   const bool valid = row < ny;
 #pragma unroll
-  for (int k = 0; k < kHankelMaxEll; ++k) {
+  for (int k = 0; k < 16 * NBU; ++k) {
     const T x = Y[(valid ? row : 0) + ny * (k < lr ? k : 0)];
     yv[k] = (valid && k < lr) ? (double)x : 0.0;
   }
   for (int j = 0; j < r; ++j) {
-    const double u = dot_row(yv, bu + j * kHankelMaxEll);
+    const double u = dot_row<NBU>(yv, bu + j * kHankelMaxEll);
     double best = valid ? fabs(u) : -1.0;
     int64_t bi = valid ? row : INT64_MAX;
     double bu_v = u;
@@ -1006,7 +1009,7 @@ __global__ __launch_bounds__(kChThreads) void hankel_argmax_kernel(FinArgs a) {
 
 // Sign of each column from the argmax partials of the instance (chunk
 // order), then U = sgn (Y B_U) and V = sgn (Z B_V) for the rows of the chunk.
-template <typename T>
+template <typename T, int NBU, int NBV>
 __global__ __launch_bounds__(kChThreads) void hankel_write_kernel(FinArgs a) {
   __shared__ __align__(16) double bu[kHankelMaxEll * kHankelMaxEll];
   __shared__ __align__(16) double bv[kHankelMaxEll * kHankelMaxEll];
@@ -1051,14 +1054,14 @@ __global__ __launch_bounds__(kChThreads) void hankel_write_kernel(FinArgs a) {
   const int64_t ny = (int64_t)a.m * s, nz = (int64_t)a.n * s;
   if (row < ny) {
     const T* Y = reinterpret_cast<const T*>(a.y) + a.t.y_off[b];
-    double yv[kHankelMaxEll];
+    double yv[16 * NBU];
 #pragma unroll
-    for (int k = 0; k < kHankelMaxEll; ++k) {
+    for (int k = 0; k < 16 * NBU; ++k) {
       const T x = Y[row + ny * (k < lr ? k : 0)];
       yv[k] = k < lr ? (double)x : 0.0;
     }
     for (int j = 0; j < r; ++j) {
-      const double u = sgn[j] * dot_row(yv, bu + j * kHankelMaxEll);
+      const double u = sgn[j] * dot_row<NBU>(yv, bu + j * kHankelMaxEll);
       const int64_t o = a.t.u_off[b] + row + ny * j;
       if (a.out_double) reinterpret_cast<double*>(a.U)[o] = u;
       else reinterpret_cast<float*>(a.U)[o] = (float)u;
@@ -1066,14 +1069,14 @@ __global__ __launch_bounds__(kChThreads) void hankel_write_kernel(FinArgs a) {
   }
   if (row < nz) {
     const T* Z = reinterpret_cast<const T*>(a.z) + a.t.z_off[b];
-    double zv[kHankelMaxEll];
+    double zv[16 * NBV];
 #pragma unroll
-    for (int k = 0; k < kHankelMaxEll; ++k) {
+    for (int k = 0; k < 16 * NBV; ++k) {
       const T x = Z[row + nz * (k < ll ? k : 0)];
       zv[k] = k < ll ? (double)x : 0.0;
     }
     for (int j = 0; j < r; ++j) {
-      const double v = sgn[j] * dot_row(zv, bv + j * kHankelMaxEll);
+      const double v = sgn[j] * dot_row<NBV>(zv, bv + j * kHankelMaxEll);
       const int64_t o = a.t.v_off[b] + row + nz * j;
       if (a.out_double) reinterpret_cast<double*>(a.V)[o] = v;
       else reinterpret_cast<float*>(a.V)[o] = (float)v;
@@ -1218,6 +1221,33 @@ HankelTables hankel_tables(const HankelPlan& p, char* ws) {
   t.chunk_inst = ib + 2 * B;
   t.queue = ib + 2 * B + p.n_chunks;
   return t;
+}
+
+// Sign pass and writes, specialised on the 16-entry blocks of ell_r and ell_l.
+template <typename T, int NBU, int NBV>
+hipError_t launch_finish_nb(int n_chunks, const FinArgs& fa, hipStream_t st) {
+  hipLaunchKernelGGL((hankel_argmax_kernel<T, NBU>), dim3(n_chunks), dim3(kChThreads), 0, st, fa);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((hankel_write_kernel<T, NBU, NBV>), dim3(n_chunks), dim3(kChThreads), 0, st, fa);
+  return hipGetLastError();
+}
+template <typename T, int NBU>
+hipError_t launch_finish_u(int nbv, int n_chunks, const FinArgs& fa, hipStream_t st) {
+  switch (nbv) {
+    case 1: return launch_finish_nb<T, NBU, 1>(n_chunks, fa, st);
+    case 2: return launch_finish_nb<T, NBU, 2>(n_chunks, fa, st);
+    default: return launch_finish_nb<T, NBU, 3>(n_chunks, fa, st);
+  }
+}
+template <typename T>
+hipError_t launch_finish(int nbu, int nbv, int n_chunks, const FinArgs& fa, hipStream_t st) {
+  static_assert(kHankelMaxEll <= 48, "three 16-entry blocks");
+  switch (nbu) {
+    case 1: return launch_finish_u<T, 1>(nbv, n_chunks, fa, st);
+    case 2: return launch_finish_u<T, 2>(nbv, n_chunks, fa, st);
+    default: return launch_finish_u<T, 3>(nbv, n_chunks, fa, st);
+  }
 }
 
 template <typename T>
@@ -1381,11 +1411,7 @@ static hipError_t launch_typed(const HankelPlan& p, const int64_t* s_host, const
   fa.ell_r = lr;
   fa.ell_l = ll;
   fa.r = p.r;
-  hipLaunchKernelGGL(hankel_argmax_kernel<T>, dim3(p.n_chunks), dim3(kChThreads), 0, st, fa);
-  e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(hankel_write_kernel<T>, dim3(p.n_chunks), dim3(kChThreads), 0, st, fa);
-  return hipGetLastError();
+  return launch_finish<T>((lr + 15) / 16, (ll + 15) / 16, p.n_chunks, fa, st);
 }
 
 hipError_t launch_hankel(const HankelPlan& p, const int64_t* s_host, const void* h, uint64_t seed,
